@@ -1,0 +1,156 @@
+/*
+ * lbprint.h -- C ABI of the MI355X (gfx950) library for the regularized
+ * colour-gradient lattice Boltzmann model of direct-writing printing
+ * (Monteferrante, Montessori, Succi, Pisignano, Lauricella, arXiv:2102.02655).
+ *
+ * One simulation ("handle") advances two population sets -- ink (Y, the
+ * paper's "yellow" colour) and air (B, "blue") -- on a D3Q19 lattice with the
+ * fused per-cell step of Sec. II.A-B:
+ *   moments (Sec. II.A), the colour gradient (Eq. (lattgrad)) with wall
+ *   densities (Eq. (wet)), the ink's local relaxation time from the strain
+ *   rate (Eqs. (notnewvisc)-(tauofgammadot)) mixed by Eq. (tauinter), the
+ *   regularised BGK collision (Eqs. (reg), (modbgk)) with exact-difference
+ *   forcing, the perturbation (Eq. (pertopform)) and recolouring operators,
+ *   streaming (Eq. (lbm)) with halfway bounce-back, moving-wall bounce-back
+ *   (Eq. (movwall)), the nozzle inlet (Eq. (movnozzle)), anti-bounce-back
+ *   pressure faces, and a moving print-head template whose released nodes are
+ *   created at equilibrium and whose covered nodes are deleted.
+ *
+ * Conventions
+ *   - Lattice units (dx = dt = 1).  Box nx * ny * nz; x and y are periodic;
+ *     the z faces are periodic, walls or pressure faces.  Cell (x, y, z) has
+ *     its centre at integer coordinates.
+ *   - Field arrays are C order [z][y][x] (numpy shape (nz, ny, nx)); velocity
+ *     arrays are [z][y][x][3].
+ *   - Colour k = 0 is the ink Y, k = 1 the air B.
+ *   - All calls return lb_status; nothing throws across the ABI.  A handle is
+ *     not thread-safe; separate handles may share a stream.
+ *
+ * Memory ownership
+ *   - The caller owns lb_params and every host array; they are read during
+ *     the call and never retained.
+ *   - The caller owns the device workspace: it allocates at least
+ *     lb_footprint() bytes (256-byte aligned) and lends it exclusively to the
+ *     handle until lb_destroy().  The library never allocates or frees device
+ *     memory on this path.
+ *   - The caller owns the HIP stream; every kernel and copy of a handle is
+ *     enqueued on it.  Only lb_moments() synchronises it.
+ */
+#ifndef LBPRINT_H
+#define LBPRINT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,    /* inconsistent parameters, bad pointer or size           */
+    LB_ENOMEM = -2,    /* workspace smaller than lb_footprint()                  */
+    LB_EDEVICE = -3,   /* a HIP call failed (message in lb_last_error)           */
+    LB_EUNSTABLE = -4, /* NaN, negative density or |u| > 0.3 detected            */
+    LB_ESTATE = -5     /* call not allowed in the handle's state                 */
+} lb_status;
+
+/* Population storage.  LB_F64: FP64 storage and arithmetic.  LB_F32: FP32
+ * storage and arithmetic (conservation sums always in FP64).  LB_BF16_DEV and
+ * LB_F16_DEV (reduced storage: populations kept as 16-bit deviations from the
+ * local equilibrium, FP32 arithmetic) are reserved: lb_create rejects them
+ * with LB_EINVAL until implemented. */
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16_DEV = 2, LB_F16_DEV = 3 } lb_storage;
+
+/* Ink rheology (Sec. II.B): constant tau_y; power law nu = K gdot^(n-1); Cross
+ * law nu = nu_inf + (nu0 - nu_inf) / (1 + (lambda gdot)^m) (Eq. (notnewvisc),
+ * the paper's flow index renamed m).  gdot is the paper's 2 |Gamma|. */
+typedef enum { LB_NEWTONIAN = 0, LB_POWER_LAW = 1, LB_CROSS = 2 } lb_rheology;
+
+typedef enum { LB_FACE_PERIODIC = 0, LB_FACE_WALL = 1, LB_FACE_PRESSURE = 2 } lb_face;
+
+typedef struct {
+    int nx, ny, nz;
+    int storage;              /* lb_storage                                                */
+    double alpha[2];          /* phi_0 of Y and B (Sec. II.A); 1/3 gives phi_i = w_i         */
+    double rho0[2];           /* pure-phase densities rho_Y^0, rho_B^0 (phase field, lid)   */
+    double A, beta;           /* perturbation amplitude (Eq. (pertopform)), recolouring beta */
+    double eps_g;             /* regulariser of |grad rho^N| in the recolouring's cos(phi)  */
+    double tau_b;             /* air relaxation time (> 1/2)                                */
+    int rheology;             /* lb_rheology                                                */
+    double tau_y;             /* Newtonian ink relaxation time                              */
+    double K, n;              /* power law                                                  */
+    double nu0, nu_inf, lambda, m; /* Cross law                                             */
+    double tau_min, tau_max;  /* clamp of the ink relaxation time (tau_min > 1/2)           */
+    double rho_eps;           /* floor of rho_Y in the strain-rate equation                 */
+    double zeta_wall[2];      /* wetting affinity of the z walls, Eq. (wet)                 */
+    double zeta_noz[2];       /* wetting affinity of the nozzle                             */
+    double drag_gamma;        /* substrate drag -gamma rho_Y (u - u_wall), Sec. II.B        */
+    double drag_range;        /* drag acts where z + 1/2 < drag_range above a z-low wall    */
+    double body_g[3];         /* body acceleration                                          */
+    int face_zlo, face_zhi;   /* lb_face; both periodic or both not                         */
+    double u_zlo[3], u_zhi[3];     /* wall velocities                                       */
+    double rho_zlo[2], rho_zhi[2]; /* densities imposed by pressure faces (Y, B)            */
+    int has_nozzle;           /* print head present (requires a non-periodic top face)      */
+    double noz_x0[2];         /* head axis (x, y) at step 0                                 */
+    double noz_v[2];          /* head velocity (x, y), constant (Sec. II.B)                 */
+    double noz_r_in;          /* bore radius                                                */
+    double noz_wall;          /* shell thickness                                            */
+    double noz_tip_z;         /* shell from z >= noz_tip_z through the top face             */
+    double u_ink[3];          /* ink velocity in the head frame, Eq. (movnozzle)            */
+    double lid_rho_y;         /* ink density imposed on the inlet lid                       */
+    int check_interval;       /* 0: checks only in lb_moments; k > 0: every k steps          */
+} lb_params;
+
+typedef struct {
+    double mass[2];           /* sum of rho_Y, rho_B over fluid cells, now (FP64)            */
+    double mom[3];            /* sum of rho u (bare, without the half-force) over fluid cells */
+    double mass_wall[2];      /* cumulative mass added by bounce-back / lid links            */
+    double mass_open[2];      /* cumulative mass added by anti-bounce-back links             */
+    double mass_created[2];   /* cumulative mass of nodes created by the moving head         */
+    double mass_deleted[2];   /* cumulative mass of nodes deleted by the moving head         */
+} lb_conserved;
+/* mass[k](t) - mass[k](0) = mass_wall + mass_open + mass_created - mass_deleted,
+ * to rounding. */
+
+typedef struct lb_handle lb_handle;
+
+/* Bytes of device workspace a handle needs for these parameters (pure host
+ * computation; used for admission).  LB_EINVAL on bad parameters. */
+lb_status lb_footprint(const lb_params *p, size_t *bytes);
+
+/* Create a simulation.  rho_y, rho_b: host FP64 [z][y][x] initial densities;
+ * u: host FP64 [z][y][x][3] initial velocity or NULL for rest.  The state is
+ * f^k = f^{k,eq}(rho^k, u) at the fluid cells of step 0 (Sec. II.A).
+ * dev_workspace: device pointer to ws_bytes >= lb_footprint() bytes.
+ * hip_stream: the hipStream_t to enqueue on (NULL = default stream).
+ * On success *out is a new handle; on failure *out is NULL. */
+lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b, const double *u,
+                    void *dev_workspace, size_t ws_bytes, void *hip_stream, lb_handle **out);
+
+/* Advance nsteps time steps (Eq. (lbm)); asynchronous on the handle's stream.
+ * LB_ESTATE after an LB_EUNSTABLE result. */
+lb_status lb_step(lb_handle *h, int nsteps);
+
+/* Fields and conserved sums at the current step.  rho_y, rho_b (N values) and
+ * u (3N values, the physical velocity (sum f c + F/2) / rho) are written as
+ * FP64 (dtype 0) or FP32 (dtype 1) into host (dst_is_device = 0) or device
+ * (dst_is_device = 1) memory; any may be NULL.  Solid cells read 0.  cons may
+ * be NULL.  Synchronises the stream.  Returns LB_EUNSTABLE (after filling the
+ * outputs) if a NaN, a negative density or |u| > 0.3 is present. */
+lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype,
+                     lb_conserved *cons);
+
+/* Current step count. */
+long lb_time(const lb_handle *h);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+lb_status lb_destroy(lb_handle *h);
+
+const char *lb_strerror(lb_status s);
+/* Last error message of a handle, or of the calling thread when h is NULL. */
+const char *lb_last_error(const lb_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,406 @@
+// lb_device.h -- per-cell device functions of the colour-gradient step.
+//
+// Population storage (both FP64 and FP32 forms): two structure-of-arrays
+// sets, x fastest,
+//   set 0: T_i = f^Y_i + f^B_i - w_i rho_ref   (the total, shifted by the
+//          reference rest state so that bulk values are small deviations)
+//   set 1: Y_i = f^Y_i                          (the ink)
+// which is a change of basis of the paper's (f^Y, f^B): f^B_i = T_i + w_i
+// rho_ref - Y_i.  Every formula below is the paper's, rewritten for this
+// basis; the shift keeps the total density, momentum and stress accurate in
+// FP32.
+//
+// The per-cell moment set carried from the pull to the collision (the
+// regularised collision needs no more than these, Eq. (reg)):
+//   0 drho = sum T_i           (rho = rho_ref + drho)
+//   1 rhoY = sum Y_i
+//   2..4   j = sum T_i c_i     (total momentum)
+//   5..10  PT = sum T_i c c    (xx, yy, zz, xy, xz, yz)
+//   11..16 PY = sum Y_i c c
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "d3q19.h"
+
+namespace lbk {
+
+constexpr int NMOM = 17;
+constexpr int NCHI = 3;   // rho^N, rho_Y/rho, rho_B/rho
+constexpr int NMAC = 5;   // rho_Y, rho_B, u (bare) for the next pull's boundary rules
+
+enum Rheo { RHEO_NEWTON = 0, RHEO_POWER = 1, RHEO_CROSS = 2 };
+enum Face { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_PRESSURE = 2 };
+enum Col { COL_OUT = 0, COL_BORE = 1, COL_SHELL = 2 };
+enum Site { ST_FLUID = 0, ST_NOZ, ST_WALL_LO, ST_WALL_HI, ST_OPEN_LO, ST_OPEN_HI, ST_LID };
+
+// Everything a kernel needs about one simulation; passed by value.
+struct DevParams {
+    int nx, ny, nz;
+    int periodic_z;
+    int face_lo, face_hi;
+    long long N;
+    double rho_ref;            // shift of set 0 (air reference density)
+    double rho0[2];            // phase-field normalisation
+    double phi[2][3];          // phi_i^k per shell
+    double phid[2][3];         // phi_i^k - w_i per shell
+    double dcs2[2];            // c_{s,k}^2 - c_s^2 (second moment of phi^k minus that of w)
+    double A, beta, eps2;
+    double tau_b;
+    int rheology;
+    double tau_y;
+    double Kp, n;              // power law: nu / c_s^2 = Kp gdot^(n-1)
+    double nu0p, nuinfp, lambda, m;  // Cross: nu / c_s^2 = nuinfp + (nu0p - nuinfp) / (1 + (lambda gdot)^m)
+    double tau_min, tau_max;
+    double s_lo, s_hi;         // shear-thinning clamp thresholds of s = S / (c_s^2 rho_Y)
+    double lg_lo, lg_hi;       // log2 of the strain rates at the clamps
+    double rho_eps;
+    double zeta_wall[2], zeta_noz[2];
+    double drag_gamma, drag_range;
+    double g[3];
+    double u_lo[3], u_hi[3];
+    double rho_lo[2], rho_hi[2];
+    int has_nozzle;
+    double ri2, ro2, rout, tip_z;
+    double vnoz[2];
+    double u_in[3];            // u_ink + v_nozzle, Eq. (movnozzle)
+    double lid_rho;
+};
+
+// Head axis of the previous and the current step, wrapped into the box.
+struct HeadPos {
+    double hx_p, hy_p, hx_c, hy_c;
+};
+
+__device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// ---------------------------------------------------------------- geometry
+// Decided in FP64 with every operation rounded as written (no FMA
+// contraction), so that the rasterised template is identical on every
+// implementation that evaluates the same expressions.
+
+__device__ __forceinline__ int column_class(const DevParams &P, double hx, double hy, int x, int y)
+{
+#pragma clang fp contract(off)
+    double dx = (double)x - hx;
+    double dy = (double)y - hy;
+    if (dx >= 0.5 * P.nx) dx -= P.nx;
+    if (dx < -0.5 * P.nx) dx += P.nx;
+    if (dy >= 0.5 * P.ny) dy -= P.ny;
+    if (dy < -0.5 * P.ny) dy += P.ny;
+    double r2 = dx * dx + dy * dy;
+    if (r2 < P.ri2) return COL_BORE;
+    if (r2 < P.ro2) return COL_SHELL;
+    return COL_OUT;
+}
+
+// True when no column within one lattice link of (x, y) can touch the shell:
+// lets bulk cells skip the FP64 geometry entirely (conservative).
+__device__ __forceinline__ bool far_from_head(const DevParams &P, double hx, double hy, int x, int y)
+{
+    if (!P.has_nozzle) return true;
+    double dx = fabs((double)x - hx), dy = fabs((double)y - hy);
+    dx = fmin(dx, (double)P.nx - dx);
+    dy = fmin(dy, (double)P.ny - dy);
+    double lim = P.rout + 3.0;
+    return dx > lim || dy > lim;
+}
+
+__device__ __forceinline__ bool is_solid(const DevParams &P, double hx, double hy, int x, int y, int z)
+{
+    if (!P.has_nozzle) return false;
+    if ((double)z < P.tip_z) return false;
+    return column_class(P, hx, hy, x, y) == COL_SHELL;
+}
+
+// Site type of (x, y, z) (x, y already wrapped); z is wrapped in place when
+// the z faces are periodic.  Above the top face the head's columns override
+// the face: bore = inlet lid, shell = nozzle solid.
+__device__ __forceinline__ int classify(const DevParams &P, double hx, double hy, int x, int y, int &z, bool near)
+{
+    if (z < 0 || z >= P.nz) {
+        if (P.periodic_z) {
+            z = wrap(z, P.nz);
+        } else {
+            bool lo = z < 0;
+            if (!lo && near) {
+                int cc = column_class(P, hx, hy, x, y);
+                if (cc == COL_BORE) return ST_LID;
+                if (cc == COL_SHELL) return ST_NOZ;
+            }
+            int face = lo ? P.face_lo : P.face_hi;
+            if (face == FACE_WALL) return lo ? ST_WALL_LO : ST_WALL_HI;
+            return lo ? ST_OPEN_LO : ST_OPEN_HI;
+        }
+    }
+    if (near && is_solid(P, hx, hy, x, y, z)) return ST_NOZ;
+    return ST_FLUID;
+}
+
+__device__ __forceinline__ long long cidx(const DevParams &P, int x, int y, int z)
+{
+    return ((long long)z * P.ny + y) * P.nx + x;
+}
+
+// --------------------------------------------------------------- moments
+
+template <typename R>
+struct Mom {
+    R m[NMOM];
+};
+
+template <typename R>
+__device__ __forceinline__ void mom_zero(Mom<R> &M)
+{
+#pragma unroll
+    for (int q = 0; q < NMOM; ++q) M.m[q] = R(0);
+}
+
+template <typename R, int I>
+__device__ __forceinline__ void mom_add(Mom<R> &M, R T, R Y)
+{
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+    M.m[0] += T;
+    M.m[1] += Y;
+    if (X) M.m[2] += X > 0 ? T : -T;
+    if (Yc) M.m[3] += Yc > 0 ? T : -T;
+    if (Z) M.m[4] += Z > 0 ? T : -T;
+    if (X) M.m[5] += T;
+    if (Yc) M.m[6] += T;
+    if (Z) M.m[7] += T;
+    if (X && Yc) M.m[8] += X * Yc > 0 ? T : -T;
+    if (X && Z) M.m[9] += X * Z > 0 ? T : -T;
+    if (Yc && Z) M.m[10] += Yc * Z > 0 ? T : -T;
+    if (X) M.m[11] += Y;
+    if (Yc) M.m[12] += Y;
+    if (Z) M.m[13] += Y;
+    if (X && Yc) M.m[14] += X * Yc > 0 ? Y : -Y;
+    if (X && Z) M.m[15] += X * Z > 0 ? Y : -Y;
+    if (Yc && Z) M.m[16] += Yc * Z > 0 ? Y : -Y;
+}
+
+// Boundary-flux accumulators of one pull (FP64): bounce-back family (Y, B),
+// anti-bounce-back (Y, B).
+struct Flux {
+    double wallY, wallB, openY, openB;
+};
+
+// Pull of one population pair (Eq. (lbm) as a pull): f_i(x, t) comes from
+// x - c_i at t-1, or, when that site is not fluid at t-1, from the boundary
+// rule applied to x's own post-collision population of the opposite link
+// (Sec. II.B: halfway bounce-back, Eq. (movwall) with the wall density
+// extrapolated inward, Eq. (movnozzle) on the lid, anti-bounce-back on
+// pressure faces).
+template <typename R, int I>
+__device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
+                                         const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
+                                         bool first, Mom<R> &M, Flux &fl)
+{
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+    constexpr int IB = lbq::opp(I);
+    const long long N = P.N;
+    const R *sT = src;
+    const R *sY = src + (long long)lbq::Q * N;
+    if (first) {
+        mom_add<R, I>(M, sT[I * N + cell], sY[I * N + cell]);
+        return;
+    }
+    int xs = X ? wrap(x - X, P.nx) : x;
+    int ys = Yc ? wrap(y - Yc, P.ny) : y;
+    int zs = z - Z;
+    int st = (Z == 0 && !near) ? ST_FLUID : classify(P, H.hx_p, H.hy_p, xs, ys, zs, near);
+    if (st == ST_FLUID) {
+        long long sc = ((long long)zs * P.ny + ys) * P.nx + xs;
+        mom_add<R, I>(M, sT[I * N + sc], sY[I * N + sc]);
+        return;
+    }
+    // the link from x towards the wall is IB; its post-collision values
+    const R Tout = sT[IB * N + cell];
+    const R Yout = sY[IB * N + cell];
+    const R wi = R(lbq::w(I));
+    R T, Yv;
+    if (st == ST_OPEN_LO || st == ST_OPEN_HI) {
+        const bool lo = st == ST_OPEN_LO;
+        const double rw0 = lo ? P.rho_lo[0] : P.rho_hi[0], rw1 = lo ? P.rho_lo[1] : P.rho_hi[1];
+        // u_w = (3 u(x) - u(x + c_i)) / 2 at t-1 when x + c_i was fluid
+        R ux = mac[2 * N + cell], uy = mac[3 * N + cell], uz = mac[4 * N + cell];
+        int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
+        int s1 = classify(P, H.hx_p, H.hy_p, x1, y1, z1, near);
+        if (s1 == ST_FLUID) {
+            long long c1 = ((long long)z1 * P.ny + y1) * P.nx + x1;
+            ux = (R(3) * ux - mac[2 * N + c1]) * R(0.5);
+            uy = (R(3) * uy - mac[3 * N + c1]) * R(0.5);
+            uz = (R(3) * uz - mac[4 * N + c1]) * R(0.5);
+        }
+        R cu = R(X) * ux + R(Yc) * uy + R(Z) * uz;
+        R uu = ux * ux + uy * uy + uz * uz;
+        R E = wi * (cu * cu * R(4.5) - uu * R(1.5));
+        R phiY = R(P.phi[0][lbq::shell(I)]), phiB = R(P.phi[1][lbq::shell(I)]);
+        R rY = R(rw0), rB = R(rw1);
+        Yv = -Yout + R(2) * rY * (phiY + E);
+        T = -Tout - R(2) * wi * R(P.rho_ref) + R(2) * (rY * phiY + rB * phiB) + R(2) * (rY + rB) * E;
+    } else {
+        double U0, U1, U2;
+        R rwY, rwB;
+        if (st == ST_LID) {
+            U0 = P.u_in[0];
+            U1 = P.u_in[1];
+            U2 = P.u_in[2];
+            rwY = R(P.lid_rho);
+            rwB = R(0);
+        } else {
+            if (st == ST_NOZ) {
+                U0 = P.vnoz[0];
+                U1 = P.vnoz[1];
+                U2 = 0.0;
+            } else {
+                const bool lo = st == ST_WALL_LO;
+                U0 = lo ? P.u_lo[0] : P.u_hi[0];
+                U1 = lo ? P.u_lo[1] : P.u_hi[1];
+                U2 = lo ? P.u_lo[2] : P.u_hi[2];
+            }
+            rwY = R(0);
+            rwB = R(0);
+            if (U0 * X + U1 * Yc + U2 * Z != 0.0) {
+                // rho_w by quadratic extrapolation to the link midpoint from
+                // x, x + c_i, x + 2 c_i (the inward direction), at t-1
+                R r0Y = mac[0 * N + cell], r0B = mac[1 * N + cell];
+                int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
+                int s1 = classify(P, H.hx_p, H.hy_p, x1, y1, z1, near);
+                if (s1 == ST_FLUID) {
+                    long long c1 = ((long long)z1 * P.ny + y1) * P.nx + x1;
+                    R r1Y = mac[0 * N + c1], r1B = mac[1 * N + c1];
+                    int x2 = X ? wrap(x1 + X, P.nx) : x1, y2 = Yc ? wrap(y1 + Yc, P.ny) : y1, z2 = z1 + Z;
+                    int s2 = classify(P, H.hx_p, H.hy_p, x2, y2, z2, near);
+                    if (s2 == ST_FLUID) {
+                        long long c2 = ((long long)z2 * P.ny + y2) * P.nx + x2;
+                        R r2Y = mac[0 * N + c2], r2B = mac[1 * N + c2];
+                        rwY = (R(15) * r0Y - R(10) * r1Y + R(3) * r2Y) * R(0.125);
+                        rwB = (R(15) * r0B - R(10) * r1B + R(3) * r2B) * R(0.125);
+                    } else {
+                        rwY = (R(3) * r0Y - r1Y) * R(0.5);
+                        rwB = (R(3) * r0B - r1B) * R(0.5);
+                    }
+                } else {
+                    rwY = r0Y;
+                    rwB = r0B;
+                }
+                rwY = rwY > R(0) ? rwY : R(0);
+                rwB = rwB > R(0) ? rwB : R(0);
+            }
+        }
+        // f_i(x, t) = f*_ibar(x, t-1) + 2 w_i rho_w (U . c_i) / c_s^2
+        R Uc = R(U0 * X + U1 * Yc + U2 * Z);
+        R k = R(6) * wi * Uc;
+        Yv = Yout + k * rwY;
+        T = Tout + k * (rwY + rwB);
+    }
+    // mass this link's rule adds, per colour (selects, not branches, so the
+    // accumulators stay in registers)
+    const bool open = st == ST_OPEN_LO || st == ST_OPEN_HI;
+    const double dY = (double)(Yv - Yout), dB = (double)(T - Tout) - dY;
+    fl.openY += open ? dY : 0.0;
+    fl.openB += open ? dB : 0.0;
+    fl.wallY += open ? 0.0 : dY;
+    fl.wallB += open ? 0.0 : dB;
+    mom_add<R, I>(M, T, Yv);
+}
+
+template <typename R, int I = 0>
+__device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
+                                         const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
+                                         bool first, Mom<R> &M, Flux &fl)
+{
+    if constexpr (I < lbq::Q) {
+        pull_one<R, I>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
+        pull_all<R, I + 1>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
+    }
+}
+
+// Colour fields of a site from its densities: rho^N (the standard phase field
+// (rho_Y/rho_Y^0 - rho_B/rho_B^0) / (rho_Y/rho_Y^0 + rho_B/rho_B^0)) and the
+// colour fractions.  Zero where the densities vanish.
+template <typename R>
+__device__ __forceinline__ void chi_of(const DevParams &P, R rY, R rB, R &cN, R &cY, R &cB)
+{
+    R a = rY * R(1.0 / P.rho0[0]), b = rB * R(1.0 / P.rho0[1]);
+    R s = a + b, t = rY + rB;
+    cN = s != R(0) ? (a - b) / s : R(0);
+    cY = t != R(0) ? rY / t : R(0);
+    cB = t != R(0) ? rB / t : R(0);
+}
+
+// ----------------------------------------------------------- rheology
+
+// Ink relaxation time from the strain rate, Eqs. (stressvsstrain) and
+// (tauofgammadot): gdot tau_Y(gdot) = s with s = |Pi^Y| / (c_s^2 rho_Y) and
+// gdot = 2|Gamma|.  The unclamped law gdot tau(gdot) is increasing, so the
+// clamped solution is clamp(tau(root of the unclamped equation)).  Power law:
+// precomputed thresholds give the clamped ends exactly; inside, Newton on
+// log2(gdot) from the right of the root (the log-sum-exp is convex, so the
+// iterates decrease monotonically), 4 steps.  Cross: Newton with a bracket.
+template <typename R>
+__device__ __forceinline__ R lg2(R v);
+template <>
+__device__ __forceinline__ float lg2<float>(float v) { return __log2f(v); }
+template <>
+__device__ __forceinline__ double lg2<double>(double v) { return log2(v); }
+template <typename R>
+__device__ __forceinline__ R ex2(R v);
+template <>
+__device__ __forceinline__ float ex2<float>(float v) { return exp2f(v); }
+template <>
+__device__ __forceinline__ double ex2<double>(double v) { return exp2(v); }
+
+template <typename R>
+__device__ __forceinline__ R tau_ink(const DevParams &P, R S, R rY)
+{
+    if (P.rheology == RHEO_NEWTON) return R(P.tau_y);
+    R r = rY > R(P.rho_eps) ? rY : R(P.rho_eps);
+    R s = S * R(3) / r;
+    const R tmin = R(P.tau_min), tmax = R(P.tau_max);
+    if (P.rheology == RHEO_POWER) {
+        if (!(s > R(P.s_lo))) return tmax;
+        if (s >= R(P.s_hi)) return tmin;
+        const R n = R(P.n), Kp = R(P.Kp);
+        const R ls = lg2<R>(s);
+        // start: the smaller of the inertial and the viscous limits, clipped
+        R x = fmin(ls + R(1), (ls - lg2<R>(Kp)) / n);
+        x = fmin(fmax(x, R(P.lg_lo)), R(P.lg_hi));
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            R a = R(0.5) * ex2<R>(x);
+            R b = Kp * ex2<R>(n * x);
+            R G = a + b;
+            R h = lg2<R>(G) - ls;
+            x -= h * G / (a + n * b);
+        }
+        R tau = R(0.5) + Kp * ex2<R>((n - R(1)) * x);
+        return fmin(fmax(tau, tmin), tmax);
+    }
+    // Cross law
+    const R m = R(P.m), lam = R(P.lambda), nuinf = R(P.nuinfp), dnu = R(P.nu0p - P.nuinfp);
+    const R t0 = R(0.5) + R(P.nu0p), tinf = R(0.5) + R(P.nuinfp);
+    if (!(s > R(0))) return fmin(fmax(t0, tmin), tmax);
+    R lo = lg2<R>(s / fmax(t0, tinf)), hi = lg2<R>(s / fmin(t0, tinf));
+    R x = hi;
+    const R ls = lg2<R>(s);
+    const R llam = lg2<R>(lam > R(0) ? lam : R(1));
+#pragma unroll 1
+    for (int it = 0; it < 12; ++it) {
+        R q = lam > R(0) ? ex2<R>(m * (llam + x)) : R(0);
+        R nu = nuinf + dnu / (R(1) + q);
+        R tau = R(0.5) + nu;
+        R h = x + lg2<R>(tau) - ls;
+        if (h > R(0)) hi = x; else lo = x;
+        R dnudx = -dnu * m * q / ((R(1) + q) * (R(1) + q));  // d nu / d log2(gdot) * ln 2 folded below
+        R hp = R(1) + dnudx / tau;
+        R xn = x - h / hp;
+        x = (xn > lo && xn < hi) ? xn : R(0.5) * (lo + hi);
+    }
+    R q = lam > R(0) ? ex2<R>(m * (llam + x)) : R(0);
+    R tau = R(0.5) + nuinf + dnu / (R(1) + q);
+    return fmin(fmax(tau, tmin), tmax);
+}
+
+}  // namespace lbk

@@ -1,0 +1,965 @@
+// lbprint.hip -- gfx950 kernels and the C ABI (include/lbprint.h) of the
+// colour-gradient lattice Boltzmann printing step (arXiv:2102.02655).
+//
+// One time step t-1 -> t is four kernels on the caller's stream:
+//   k_moments  pull f(t) from the post-collision state of t-1 (Eq. (lbm),
+//              boundary rules of Sec. II.B), reduce it to the moment set,
+//              colour fields; deleted nodes' mass and boundary fluxes (FP64)
+//   k_create   nodes released by the moving head: f^eq(rho_bar, v_nozzle)
+//   k_wall     fictitious wall densities, Eq. (wet), in-box and ghost layers
+//   k_collide  colour gradient (Eq. (lattgrad)), rheology, regularised
+//              collision, perturbation, recolouring; store at the cell
+// The stored state between steps is the post-collision population pair.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbprint.h"
+#include "lb_collide.h"
+#include "lb_device.h"
+
+using namespace lbk;
+
+namespace {
+
+constexpr int TPB = 256;       // threads per block of the per-cell kernels
+constexpr int NB_SPARSE = 64;  // fixed grid of the head-box kernels (deterministic slots)
+constexpr int NSLOT = 6;       // per-block FP64 sums: wall Y, wall B, open Y, open B, deleted Y, deleted B
+constexpr int NPART = 6;       // per-block FP64 sums of the output: mass Y, B, momentum xyz, unstable
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum of NV doubles (fixed shuffle and wave order);
+// thread 0 adds (accumulate) or writes the result to slot[0..NV).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *slot, bool accumulate)
+{
+    __shared__ double red[NV][TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) red[q][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[q][w];
+            slot[q] = accumulate ? slot[q] + s : s;
+        }
+    }
+}
+
+__device__ __forceinline__ void cell_xyz(const DevParams &P, long long cell, int &x, int &y, int &z)
+{
+    long long plane = (long long)P.nx * P.ny;
+    z = (int)(cell / plane);
+    long long r = cell - (long long)z * plane;
+    y = (int)(r / P.nx);
+    x = (int)(r - (long long)y * P.nx);
+}
+
+template <typename R>
+__device__ __forceinline__ void write_chi(const DevParams &P, R *chi, long long cell, R rY, R rB)
+{
+    R cN, cY, cB;
+    chi_of<R>(P, rY, rB, cN, cY, cB);
+    chi[cell] = cN;
+    chi[P.N + cell] = cY;
+    chi[2 * P.N + cell] = cB;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Initial state: f^k = f^{k,eq}(rho^k, u) at the fluid cells of step 0.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_init(DevParams P, HeadPos H, const double *__restrict__ rho_y,
+                                              const double *__restrict__ rho_b, const double *__restrict__ u,
+                                              int has_u, R *__restrict__ dst)
+{
+    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
+    if (cell >= P.N) return;
+    int x, y, z;
+    cell_xyz(P, cell, x, y, z);
+    R *dT = dst, *dY = dst + (long long)lbq::Q * P.N;
+    bool solid = !far_from_head(P, H.hx_c, H.hy_c, x, y) && is_solid(P, H.hx_c, H.hy_c, x, y, z);
+    double rY = rho_y[cell], rB = rho_b[cell];
+    double ux = has_u ? u[3 * cell] : 0.0, uy = has_u ? u[3 * cell + 1] : 0.0, uz = has_u ? u[3 * cell + 2] : 0.0;
+    double uu = ux * ux + uy * uy + uz * uz;
+    for (int i = 0; i < lbq::Q; ++i) {
+        if (solid) {
+            dT[i * P.N + cell] = R(0);
+            dY[i * P.N + cell] = R(0);
+            continue;
+        }
+        int sh = lbq::shell(i);
+        double wi = lbq::w(i);
+        double cu = lbq::cx(i) * ux + lbq::cy(i) * uy + lbq::cz(i) * uz;
+        double E = wi * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        double fY = rY * (P.phi[0][sh] + E);
+        double T = rY * P.phid[0][sh] + rB * P.phid[1][sh] + (rY + rB - P.rho_ref) * wi + (rY + rB) * E;
+        dT[i * P.N + cell] = R(T);
+        dY[i * P.N + cell] = R(fY);
+    }
+}
+
+// Pull + moments.  commit = 1 adds this step's boundary fluxes and deleted
+// mass into the block's cumulative slot; commit = 0 writes them (pending
+// values for lb_moments) without touching the cumulative state.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R *__restrict__ src,
+                                                 const R *__restrict__ mac, R *__restrict__ mom, R *__restrict__ chi,
+                                                 double *__restrict__ slots, int first, int commit)
+{
+    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
+    double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
+    int any = 0;
+    if (cell < P.N) {
+        int x, y, z;
+        cell_xyz(P, cell, x, y, z);
+        bool near = !far_from_head(P, H.hx_p, H.hy_p, x, y) || !far_from_head(P, H.hx_c, H.hy_c, x, y);
+        bool sp = near && is_solid(P, H.hx_p, H.hy_p, x, y, z);
+        bool sc = near && is_solid(P, H.hx_c, H.hy_c, x, y, z);
+        if (!sp) {
+            Mom<R> M;
+            mom_zero(M);
+            Flux fl = {0.0, 0.0, 0.0, 0.0};
+            pull_all<R>(P, H, src, mac, x, y, z, cell, near, first != 0, M, fl);
+            if (!sc) {
+#pragma unroll
+                for (int q = 0; q < NMOM; ++q) mom[q * P.N + cell] = M.m[q];
+                write_chi<R>(P, chi, cell, M.m[1], R(P.rho_ref) + M.m[0] - M.m[1]);
+            } else {
+                acc[4] = (double)M.m[1];
+                acc[5] = (double)(R(P.rho_ref) + M.m[0] - M.m[1]);
+            }
+            acc[0] = fl.wallY;
+            acc[1] = fl.wallB;
+            acc[2] = fl.openY;
+            acc[3] = fl.openB;
+            any = (fl.wallY != 0.0) | (fl.wallB != 0.0) | (fl.openY != 0.0) | (fl.openB != 0.0) | sc;
+        }
+    }
+    if (commit) {
+        if (!__syncthreads_or(any)) return;
+        block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, true);
+    } else {
+        block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, false);
+    }
+}
+
+// Sec. II.B: nodes released by the head (solid at t-1, fluid at t) start at
+// f^{k,eq}(rho_bar^k, v_nozzle), rho_bar^k the mean over the lattice
+// neighbours fluid at both steps (pure air rho_B^0 if there is none).  Only
+// the moment set and the colour fields are needed downstream.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0, int by0, int bz0, int bw, int bh,
+                                                int bd, R *__restrict__ mom, R *__restrict__ chi,
+                                                double *__restrict__ slots, int commit)
+{
+    double acc[2] = {0.0, 0.0};
+    const long long total = (long long)bw * bh * bd;
+    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+        int ix = (int)(k % bw), iy = (int)((k / bw) % bh), iz = (int)(k / ((long long)bw * bh));
+        int x = ((bx0 + ix) % P.nx + P.nx) % P.nx, y = ((by0 + iy) % P.ny + P.ny) % P.ny, z = bz0 + iz;
+        if (z < 0 || z >= P.nz) continue;
+        if (!is_solid(P, H.hx_p, H.hy_p, x, y, z) || is_solid(P, H.hx_c, H.hy_c, x, y, z)) continue;
+        double sY = 0.0, sB = 0.0;
+        int cnt = 0;
+        for (int i = 1; i < lbq::Q; ++i) {
+            int zz = z + lbq::cz(i);
+            if (P.periodic_z) zz = wrap(zz, P.nz);
+            if (zz < 0 || zz >= P.nz) continue;
+            int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
+            if (is_solid(P, H.hx_p, H.hy_p, xx, yy, zz) || is_solid(P, H.hx_c, H.hy_c, xx, yy, zz)) continue;
+            long long nb = cidx(P, xx, yy, zz);
+            double rY = (double)mom[P.N + nb];
+            double rB = (double)(R(P.rho_ref) + mom[nb] - mom[P.N + nb]);
+            sY += rY;
+            sB += rB;
+            ++cnt;
+        }
+        double rY = cnt ? sY / cnt : 0.0, rB = cnt ? sB / cnt : P.rho0[1];
+        long long cell = cidx(P, x, y, z);
+        // moments of f^eq(rho_bar, v): drho, rho_Y, j = rho v, second moments
+        double vx = P.vnoz[0], vy = P.vnoz[1];
+        double rho = rY + rB;
+        double cs2 = 1.0 / 3.0;
+        double iso = rY * P.dcs2[0] + rB * P.dcs2[1] + (rho - P.rho_ref) * cs2;
+        double cY2 = cs2 + P.dcs2[0];
+        double m[NMOM] = {rho - P.rho_ref, rY, rho * vx, rho * vy, 0.0,
+                          iso + rho * vx * vx, iso + rho * vy * vy, iso, rho * vx * vy, 0.0, 0.0,
+                          rY * (cY2 + vx * vx), rY * (cY2 + vy * vy), rY * cY2, rY * vx * vy, 0.0, 0.0};
+        for (int q = 0; q < NMOM; ++q) mom[q * P.N + cell] = R(m[q]);
+        write_chi<R>(P, chi, cell, R(rY), R(rB));
+        acc[0] += rY;
+        acc[1] += rB;
+    }
+    block_sum<2>(acc, slots + (long long)blockIdx.x * 2, commit != 0);
+}
+
+// Fictitious densities of the head's solid cells that touch fluid, Eq. (wet):
+// rho_s^k = zeta^k sum_i w_i s_i rho^k(x + c_i) / sum_i w_i s_i.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_wall(DevParams P, HeadPos H, int bx0, int by0, int bz0, int bw, int bh,
+                                              int bd, const R *__restrict__ mom, R *__restrict__ chi)
+{
+    const long long total = (long long)bw * bh * bd;
+    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+        int ix = (int)(k % bw), iy = (int)((k / bw) % bh), iz = (int)(k / ((long long)bw * bh));
+        int x = ((bx0 + ix) % P.nx + P.nx) % P.nx, y = ((by0 + iy) % P.ny + P.ny) % P.ny, z = bz0 + iz;
+        if (z < 0 || z >= P.nz) continue;
+        if (!is_solid(P, H.hx_c, H.hy_c, x, y, z)) continue;
+        double nY = 0.0, nB = 0.0, den = 0.0;
+        for (int i = 1; i < lbq::Q; ++i) {
+            int zz = z + lbq::cz(i);
+            if (P.periodic_z) zz = wrap(zz, P.nz);
+            if (zz < 0 || zz >= P.nz) continue;
+            int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
+            if (is_solid(P, H.hx_c, H.hy_c, xx, yy, zz)) continue;
+            long long nb = cidx(P, xx, yy, zz);
+            double wi = lbq::w(i);
+            double rY = (double)mom[P.N + nb];
+            double rB = (double)(R(P.rho_ref) + mom[nb] - mom[P.N + nb]);
+            nY += wi * rY;
+            nB += wi * rB;
+            den += wi;
+        }
+        long long cell = cidx(P, x, y, z);
+        R sY = den > 0.0 ? R(P.zeta_noz[0] * nY / den) : R(0);
+        R sB = den > 0.0 ? R(P.zeta_noz[1] * nB / den) : R(0);
+        write_chi<R>(P, chi, cell, sY, sB);
+    }
+}
+
+// Colour fields of the ghost layers below (face 0) and above (face 1) the
+// box: walls carry Eq. (wet)'s fictitious densities from the adjacent fluid
+// layer, pressure faces their imposed densities, the inlet lid pure ink, the
+// head's shell columns above the top the nozzle's fictitious densities.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const R *__restrict__ mom,
+                                               R *__restrict__ ghost)
+{
+    long long plane = (long long)P.nx * P.ny;
+    long long k = (long long)blockIdx.x * TPB + threadIdx.x;
+    if (k >= 2 * plane) return;
+    int face = (int)(k / plane);
+    long long c = k - face * plane;
+    int y = (int)(c / P.nx), x = (int)(c - (long long)y * P.nx);
+    int zg = face == 0 ? -1 : P.nz;
+    int zin = face == 0 ? 0 : P.nz - 1;
+    double rY, rB;
+    int kind;  // 0 = wall-like (zeta), 1 = fixed
+    double z0 = P.zeta_wall[0], z1 = P.zeta_wall[1];
+    if (face == 1 && P.has_nozzle && column_class(P, H.hx_c, H.hy_c, x, y) != COL_OUT) {
+        if (column_class(P, H.hx_c, H.hy_c, x, y) == COL_BORE) {
+            kind = 1;
+            rY = P.lid_rho;
+            rB = 0.0;
+        } else {
+            kind = 0;
+            z0 = P.zeta_noz[0];
+            z1 = P.zeta_noz[1];
+        }
+    } else {
+        int f = face == 0 ? P.face_lo : P.face_hi;
+        if (f == FACE_WALL) {
+            kind = 0;
+        } else {
+            kind = 1;
+            rY = face == 0 ? P.rho_lo[0] : P.rho_hi[0];
+            rB = face == 0 ? P.rho_lo[1] : P.rho_hi[1];
+        }
+    }
+    if (kind == 0) {
+        double nY = 0.0, nB = 0.0, den = 0.0;
+        for (int i = 1; i < lbq::Q; ++i) {
+            if (zg + lbq::cz(i) != zin) continue;
+            int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
+            if (is_solid(P, H.hx_c, H.hy_c, xx, yy, zin)) continue;
+            long long nb = cidx(P, xx, yy, zin);
+            double wi = lbq::w(i);
+            nY += wi * (double)mom[P.N + nb];
+            nB += wi * (double)(R(P.rho_ref) + mom[nb] - mom[P.N + nb]);
+            den += wi;
+        }
+        rY = den > 0.0 ? z0 * nY / den : 0.0;
+        rB = den > 0.0 ? z1 * nB / den : 0.0;
+    }
+    R cN, cY, cB;
+    chi_of<R>(P, R(rY), R(rB), cN, cY, cB);
+    ghost[(face * 3 + 0) * plane + c] = cN;
+    ghost[(face * 3 + 1) * plane + c] = cY;
+    ghost[(face * 3 + 2) * plane + c] = cB;
+}
+
+template <typename R>
+__device__ __forceinline__ void chi_at(const DevParams &P, const R *__restrict__ chi, const R *__restrict__ ghost,
+                                       int x, int y, int z, R &cN, R &cY, R &cB)
+{
+    if (z < 0 || z >= P.nz) {
+        if (P.periodic_z) {
+            z = wrap(z, P.nz);
+        } else {
+            long long plane = (long long)P.nx * P.ny;
+            int face = z < 0 ? 0 : 1;
+            long long c = (long long)y * P.nx + x;
+            cN = ghost[(face * 3 + 0) * plane + c];
+            cY = ghost[(face * 3 + 1) * plane + c];
+            cB = ghost[(face * 3 + 2) * plane + c];
+            return;
+        }
+    }
+    long long c = cidx(P, x, y, z);
+    cN = chi[c];
+    cY = chi[P.N + c];
+    cB = chi[2 * P.N + c];
+}
+
+// Colour gradients of Eq. (lattgrad), summed over opposite link pairs.
+template <typename R, int I = 1>
+__device__ __forceinline__ void grad_pairs(const DevParams &P, const R *__restrict__ chi, const R *__restrict__ ghost,
+                                           int x, int y, int z, Grad<R> &G)
+{
+    if constexpr (I < lbq::Q) {
+        constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+        R aN, aY, aB, bN, bY, bB;
+        chi_at<R>(P, chi, ghost, wrap(x + X, P.nx), wrap(y + Yc, P.ny), z + Z, aN, aY, aB);
+        chi_at<R>(P, chi, ghost, wrap(x - X, P.nx), wrap(y - Yc, P.ny), z - Z, bN, bY, bB);
+        const R k = R(3.0 * lbq::w(I));
+        const R dN = k * (aN - bN), dY = k * (aY - bY), dB = k * (aB - bB);
+        if (X) {
+            G.g[0] += X > 0 ? dN : -dN;
+            G.g[3] += X > 0 ? dY : -dY;
+            G.g[6] += X > 0 ? dB : -dB;
+        }
+        if (Yc) {
+            G.g[1] += Yc > 0 ? dN : -dN;
+            G.g[4] += Yc > 0 ? dY : -dY;
+            G.g[7] += Yc > 0 ? dB : -dB;
+        }
+        if (Z) {
+            G.g[2] += Z > 0 ? dN : -dN;
+            G.g[5] += Z > 0 ? dY : -dY;
+            G.g[8] += Z > 0 ? dB : -dB;
+        }
+        grad_pairs<R, I + 2>(P, chi, ghost, x, y, z, G);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_collide(DevParams P, HeadPos H, const R *__restrict__ mom,
+                                                 const R *__restrict__ chi, const R *__restrict__ ghost,
+                                                 R *__restrict__ dst, R *__restrict__ mac)
+{
+    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
+    if (cell >= P.N) return;
+    int x, y, z;
+    cell_xyz(P, cell, x, y, z);
+    bool near = !far_from_head(P, H.hx_c, H.hy_c, x, y);
+    if (near && is_solid(P, H.hx_c, H.hy_c, x, y, z)) return;
+    Mom<R> M;
+#pragma unroll
+    for (int q = 0; q < NMOM; ++q) M.m[q] = mom[q * P.N + cell];
+    Grad<R> G;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) G.g[q] = R(0);
+    grad_pairs<R>(P, chi, ghost, x, y, z, G);
+    R rY, rB, u[3];
+    collide_store<R>(P, M, G, z, dst, dst + (long long)lbq::Q * P.N, cell, P.N, rY, rB, u);
+    mac[cell] = rY;
+    mac[P.N + cell] = rB;
+    mac[2 * P.N + cell] = u[0];
+    mac[3 * P.N + cell] = u[1];
+    mac[4 * P.N + cell] = u[2];
+}
+
+// Fields for lb_moments: rho_Y, rho_B, physical velocity (j + F/2)/rho; block
+// sums of mass and momentum; instability flag.
+template <typename R, typename O>
+__global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const R *__restrict__ mom,
+                                                O *__restrict__ ory, O *__restrict__ orb, O *__restrict__ ou,
+                                                double *__restrict__ part)
+{
+    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
+    double acc[NPART] = {0, 0, 0, 0, 0, 0};
+    if (cell < P.N) {
+        int x, y, z;
+        cell_xyz(P, cell, x, y, z);
+        bool solid = !far_from_head(P, H.hx_c, H.hy_c, x, y) && is_solid(P, H.hx_c, H.hy_c, x, y, z);
+        double rY = 0.0, rB = 0.0, U[3] = {0.0, 0.0, 0.0};
+        if (!solid) {
+            R drho = mom[cell], rYr = mom[P.N + cell];
+            R rho = R(P.rho_ref) + drho;
+            rY = (double)rYr;
+            rB = (double)(rho - rYr);
+            double r = (double)rho;
+            double j[3] = {(double)mom[2 * P.N + cell], (double)mom[3 * P.N + cell], (double)mom[4 * P.N + cell]};
+            double F[3];
+            for (int a = 0; a < 3; ++a) F[a] = r * P.g[a];
+            if (P.drag_gamma != 0.0 && P.face_lo == FACE_WALL && (double)z + 0.5 < P.drag_range)
+                for (int a = 0; a < 3; ++a) F[a] -= P.drag_gamma * rY * (j[a] / r - P.u_lo[a]);
+            for (int a = 0; a < 3; ++a) U[a] = (j[a] + 0.5 * F[a]) / r;
+            acc[0] = rY;
+            acc[1] = rB;
+            acc[2] = j[0];
+            acc[3] = j[1];
+            acc[4] = j[2];
+            double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+            bool bad = !(r > 0.0) || !(uu <= 0.09) || rY != rY || rB != rB;
+            acc[5] = bad ? 1.0 : 0.0;
+        }
+        if (ory) ory[cell] = O(rY);
+        if (orb) orb[cell] = O(rB);
+        if (ou) {
+            ou[3 * cell] = O(U[0]);
+            ou[3 * cell + 1] = O(U[1]);
+            ou[3 * cell + 2] = O(U[2]);
+        }
+    }
+    block_sum<NPART>(acc, part + (long long)blockIdx.x * NPART, false);
+}
+
+// Deterministic final sums for lb_moments (one block):
+// out = mass[2], mom[3], wall[2], open[2], created[2], deleted[2], unstable.
+__global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part, const double *__restrict__ cum,
+                                                const double *__restrict__ pend, long long nbm,
+                                                const double *__restrict__ cumc, const double *__restrict__ pendc,
+                                                int nbc, double *__restrict__ out)
+{
+    double v[14] = {0};
+    for (long long b = threadIdx.x; b < nbm; b += TPB) {
+        const double *p = part + b * NPART;
+        for (int q = 0; q < 5; ++q) v[q] += p[q];
+        v[13] = fmax(v[13], p[5]);
+        const double *c = cum + b * NSLOT, *d = pend + b * NSLOT;
+        v[5] += c[0] + d[0];
+        v[6] += c[1] + d[1];
+        v[7] += c[2] + d[2];
+        v[8] += c[3] + d[3];
+        v[11] += c[4] + d[4];
+        v[12] += c[5] + d[5];
+    }
+    for (int b = threadIdx.x; b < nbc; b += TPB) {
+        v[9] += cumc[2 * b] + pendc[2 * b];
+        v[10] += cumc[2 * b + 1] + pendc[2 * b + 1];
+    }
+    __shared__ double red[14][TPB];
+    for (int q = 0; q < 14; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < 14; ++q)
+                red[q][threadIdx.x] =
+                    q == 13 ? fmax(red[q][threadIdx.x], red[q][threadIdx.x + s]) : red[q][threadIdx.x] + red[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 14; ++q) out[q] = red[q][0];
+}
+
+}  // namespace
+
+// ====================================================================== host
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t ALIGN = 256;
+size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+struct Layout {
+    size_t pops, mom, chi, ghost, mac, cum, pend, part, cumc, pendc, red, total;
+    long long nbm;
+};
+
+size_t real_size(int storage) { return storage == LB_F64 ? 8 : 4; }
+
+Layout layout_of(const lb_params &p)
+{
+    Layout L;
+    long long N = (long long)p.nx * p.ny * p.nz;
+    size_t rs = real_size(p.storage);
+    L.nbm = (N + TPB - 1) / TPB;
+    size_t off = 0;
+    L.pops = off;
+    off += 2 * al(2 * lbq::Q * (size_t)N * rs);
+    L.mom = off;
+    off += al(NMOM * (size_t)N * rs);
+    L.chi = off;
+    off += al(NCHI * (size_t)N * rs);
+    L.ghost = off;
+    off += al(2 * NCHI * (size_t)p.nx * p.ny * rs);
+    L.mac = off;
+    off += al(NMAC * (size_t)N * rs);
+    L.cum = off;
+    off += al((size_t)L.nbm * NSLOT * 8);
+    L.pend = off;
+    off += al((size_t)L.nbm * NSLOT * 8);
+    L.part = off;
+    off += al((size_t)L.nbm * NPART * 8);
+    L.cumc = off;
+    off += al(NB_SPARSE * 2 * 8);
+    L.pendc = off;
+    off += al(NB_SPARSE * 2 * 8);
+    L.red = off;
+    off += al(16 * 8);
+    L.total = off;
+    return L;
+}
+
+const char *validate(const lb_params &p)
+{
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "box dimensions must be positive";
+    if ((long long)p.nx * p.ny * p.nz > (1LL << 34)) return "box too large";
+    if (p.storage != LB_F64 && p.storage != LB_F32) return "storage form not implemented (LB_F64 and LB_F32 only)";
+    if (!(p.tau_b > 0.5)) return "tau_b must exceed 1/2";
+    if (p.rheology < 0 || p.rheology > 2) return "unknown rheology";
+    if (p.rheology == LB_NEWTONIAN && !(p.tau_y > 0.5)) return "tau_y must exceed 1/2";
+    if (p.rheology != LB_NEWTONIAN && !(p.tau_min > 0.5 && p.tau_max >= p.tau_min)) return "need 1/2 < tau_min <= tau_max";
+    if (p.rheology == LB_POWER_LAW && !(p.K > 0.0 && p.n > 0.0 && p.n <= 1.0)) return "power law needs K > 0, 0 < n <= 1";
+    if (p.rheology == LB_CROSS && !(p.nu0 > 0.0 && p.nu_inf > 0.0 && p.lambda >= 0.0 && p.m > 0.0 && p.m < 1.0))
+        return "Cross law needs nu0, nu_inf > 0, lambda >= 0, 0 < m < 1";
+    if (!(p.rho0[0] > 0.0 && p.rho0[1] > 0.0)) return "rho0 must be positive";
+    if (p.face_zlo < 0 || p.face_zlo > 2 || p.face_zhi < 0 || p.face_zhi > 2) return "unknown face type";
+    if ((p.face_zlo == LB_FACE_PERIODIC) != (p.face_zhi == LB_FACE_PERIODIC)) return "z faces must be both periodic or neither";
+    if (p.has_nozzle) {
+        if (p.face_zhi == LB_FACE_PERIODIC) return "a nozzle needs a non-periodic top face";
+        if (!(p.noz_tip_z >= 0.0 && p.noz_tip_z <= p.nz - 1)) return "nozzle tip outside the box";
+        if (!(p.noz_r_in > 0.0 && p.noz_wall > 0.0)) return "nozzle radii must be positive";
+        if (!(std::fabs(p.noz_v[0]) < 1.0 && std::fabs(p.noz_v[1]) < 1.0)) return "head speed must be below one cell per step";
+    }
+    if (p.eps_g < 0.0 || p.rho_eps <= 0.0) return "eps_g >= 0 and rho_eps > 0 required";
+    return nullptr;
+}
+
+DevParams make_dev(const lb_params &p)
+{
+#pragma clang fp contract(off)
+    DevParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.nx = p.nx;
+    P.ny = p.ny;
+    P.nz = p.nz;
+    P.N = (long long)p.nx * p.ny * p.nz;
+    P.periodic_z = p.face_zlo == LB_FACE_PERIODIC;
+    P.face_lo = p.face_zlo;
+    P.face_hi = p.face_zhi;
+    P.rho_ref = p.rho0[1];
+    P.rho0[0] = p.rho0[0];
+    P.rho0[1] = p.rho0[1];
+    const double cs2 = 1.0 / 3.0, w0 = 1.0 / 3.0;
+    for (int k = 0; k < 2; ++k) {
+        double a = p.alpha[k];
+        for (int s = 0; s < 3; ++s) {
+            double ws = lbq::w_of_shell(s);
+            P.phi[k][s] = s == 0 ? a : (1.0 - a) * ws / (1.0 - w0);
+            P.phid[k][s] = P.phi[k][s] - ws;
+        }
+        P.dcs2[k] = (1.0 - a) * cs2 / (1.0 - w0) - cs2;
+    }
+    P.A = p.A;
+    P.beta = p.beta;
+    P.eps2 = p.eps_g * p.eps_g;
+    P.tau_b = p.tau_b;
+    P.rheology = p.rheology;
+    P.tau_y = p.tau_y;
+    P.tau_min = p.tau_min;
+    P.tau_max = p.tau_max;
+    P.rho_eps = p.rho_eps;
+    if (p.rheology == LB_POWER_LAW) {
+        P.Kp = p.K / cs2;
+        P.n = p.n;
+        if (p.n == 1.0) {  // Newtonian in disguise
+            P.rheology = RHEO_NEWTON;
+            double t = 0.5 + P.Kp;
+            P.tau_y = t < p.tau_min ? p.tau_min : (t > p.tau_max ? p.tau_max : t);
+        } else {
+            double g1 = std::pow((p.tau_max - 0.5) / P.Kp, 1.0 / (p.n - 1.0));
+            double g2 = std::pow((p.tau_min - 0.5) / P.Kp, 1.0 / (p.n - 1.0));
+            P.s_lo = g1 * p.tau_max;
+            P.s_hi = g2 * p.tau_min;
+            P.lg_lo = std::log2(g1);
+            P.lg_hi = std::log2(g2);
+        }
+    } else if (p.rheology == LB_CROSS) {
+        P.nu0p = p.nu0 / cs2;
+        P.nuinfp = p.nu_inf / cs2;
+        P.lambda = p.lambda;
+        P.m = p.m;
+    }
+    for (int k = 0; k < 2; ++k) {
+        P.zeta_wall[k] = p.zeta_wall[k];
+        P.zeta_noz[k] = p.zeta_noz[k];
+        P.rho_lo[k] = p.rho_zlo[k];
+        P.rho_hi[k] = p.rho_zhi[k];
+    }
+    P.drag_gamma = p.drag_gamma;
+    P.drag_range = p.drag_range;
+    for (int a = 0; a < 3; ++a) {
+        P.g[a] = p.body_g[a];
+        P.u_lo[a] = p.u_zlo[a];
+        P.u_hi[a] = p.u_zhi[a];
+    }
+    P.has_nozzle = p.has_nozzle;
+    if (p.has_nozzle) {
+        P.ri2 = p.noz_r_in * p.noz_r_in;
+        double ro = p.noz_r_in + p.noz_wall;
+        P.ro2 = ro * ro;
+        P.rout = ro;
+        P.tip_z = p.noz_tip_z;
+        P.vnoz[0] = p.noz_v[0];
+        P.vnoz[1] = p.noz_v[1];
+        P.u_in[0] = p.u_ink[0] + p.noz_v[0];
+        P.u_in[1] = p.u_ink[1] + p.noz_v[1];
+        P.u_in[2] = p.u_ink[2];
+        P.lid_rho = p.lid_rho_y;
+    }
+    return P;
+}
+
+// Head axis at step t: x = x0 + v t, wrapped into [0, n).  Rounded as
+// written (no contraction) so every implementation rasterises identically.
+void head_at(const lb_params &p, long t, double *hx, double *hy, double *ux, double *uy)
+{
+#pragma clang fp contract(off)
+    double x = p.noz_x0[0] + p.noz_v[0] * (double)t;
+    double y = p.noz_x0[1] + p.noz_v[1] * (double)t;
+    *ux = x;
+    *uy = y;
+    *hx = x - (double)p.nx * std::floor(x / (double)p.nx);
+    *hy = y - (double)p.ny * std::floor(y / (double)p.ny);
+}
+
+}  // namespace
+
+struct lb_handle {
+    lb_params p;
+    DevParams P;
+    Layout L;
+    hipStream_t stream;
+    char *ws;
+    int cur;
+    long t;
+    int first;
+    int unstable;
+    std::string err;
+};
+
+namespace {
+
+lb_status fail(lb_handle *h, lb_status s, const std::string &msg)
+{
+    if (h) h->err = msg;
+    g_err = msg;
+    return s;
+}
+
+lb_status check_launch(lb_handle *h, const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(h, LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return LB_OK;
+}
+
+template <typename R>
+R *as(lb_handle *h, size_t off)
+{
+    return reinterpret_cast<R *>(h->ws + off);
+}
+
+HeadPos heads(const lb_handle *h, double *bx_lo, double *bx_hi, double *by_lo, double *by_hi)
+{
+    HeadPos H;
+    double ux_c = 0, uy_c = 0, ux_p = 0, uy_p = 0;
+    head_at(h->p, h->t, &H.hx_c, &H.hy_c, &ux_c, &uy_c);
+    if (h->first) {
+        H.hx_p = H.hx_c;
+        H.hy_p = H.hy_c;
+        ux_p = ux_c;
+        uy_p = uy_c;
+    } else {
+        head_at(h->p, h->t - 1, &H.hx_p, &H.hy_p, &ux_p, &uy_p);
+    }
+    if (bx_lo) {
+        *bx_lo = std::fmin(ux_p, ux_c);
+        *bx_hi = std::fmax(ux_p, ux_c);
+        *by_lo = std::fmin(uy_p, uy_c);
+        *by_hi = std::fmax(uy_p, uy_c);
+    }
+    return H;
+}
+
+struct Box {
+    int x0, y0, z0, w, h, d;
+};
+
+Box head_box(const lb_handle *h, double xlo, double xhi, double ylo, double yhi)
+{
+    Box b;
+    double r = h->P.rout + 2.0;
+    b.x0 = (int)std::floor(xlo - r);
+    b.y0 = (int)std::floor(ylo - r);
+    b.w = (int)std::ceil(xhi + r) - b.x0 + 1;
+    b.h = (int)std::ceil(yhi + r) - b.y0 + 1;
+    if (b.w > h->p.nx) {
+        b.w = h->p.nx;
+        b.x0 = 0;
+    }
+    if (b.h > h->p.ny) {
+        b.h = h->p.ny;
+        b.y0 = 0;
+    }
+    b.z0 = (int)std::floor(h->P.tip_z);
+    if (b.z0 < 0) b.z0 = 0;
+    b.d = h->p.nz - b.z0;
+    return b;
+}
+
+template <typename R>
+lb_status run_moments(lb_handle *h, int commit)
+{
+    double xl, xh, yl, yh;
+    HeadPos H = heads(h, &xl, &xh, &yl, &yh);
+    const Layout &L = h->L;
+    R *src = as<R>(h, L.pops + h->cur * al(2 * lbq::Q * (size_t)h->P.N * sizeof(R)));
+    double *slots = as<double>(h, commit ? L.cum : L.pend);
+    hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, src, as<R>(h, L.mac),
+                       as<R>(h, L.mom), as<R>(h, L.chi), slots, h->first, commit);
+    if (lb_status s = check_launch(h, "k_moments")) return s;
+    if (h->p.has_nozzle && !h->first) {
+        Box b = head_box(h, xl, xh, yl, yh);
+        hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h,
+                           b.d, as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, commit ? L.cumc : L.pendc), commit);
+        if (lb_status s = check_launch(h, "k_create")) return s;
+    } else if (!commit) {
+        if (hipMemsetAsync(as<double>(h, L.pendc), 0, NB_SPARSE * 2 * 8, h->stream) != hipSuccess)
+            return fail(h, LB_EDEVICE, "hipMemsetAsync");
+    }
+    return LB_OK;
+}
+
+template <typename R>
+lb_status run_step(lb_handle *h)
+{
+    if (lb_status s = run_moments<R>(h, 1)) return s;
+    double xl, xh, yl, yh;
+    HeadPos H = heads(h, &xl, &xh, &yl, &yh);
+    const Layout &L = h->L;
+    if (h->p.has_nozzle) {
+        Box b = head_box(h, xl, xh, yl, yh);
+        long long tot = (long long)b.w * b.h * b.d;
+        unsigned nb = (unsigned)std::min<long long>((tot + TPB - 1) / TPB, 4096);
+        hipLaunchKernelGGL(k_wall<R>, dim3(nb), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h, b.d,
+                           as<R>(h, L.mom), as<R>(h, L.chi));
+        if (lb_status s = check_launch(h, "k_wall")) return s;
+    }
+    if (!h->P.periodic_z) {
+        long long n = 2LL * h->p.nx * h->p.ny;
+        hipLaunchKernelGGL(k_ghost<R>, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, h->stream, h->P, H,
+                           as<R>(h, L.mom), as<R>(h, L.ghost));
+        if (lb_status s = check_launch(h, "k_ghost")) return s;
+    }
+    size_t psz = al(2 * lbq::Q * (size_t)h->P.N * sizeof(R));
+    R *dst = as<R>(h, L.pops + (1 - h->cur) * psz);
+    hipLaunchKernelGGL(k_collide<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, as<R>(h, L.mom),
+                       as<R>(h, L.chi), as<R>(h, L.ghost), dst, as<R>(h, L.mac));
+    if (lb_status s = check_launch(h, "k_collide")) return s;
+    h->cur = 1 - h->cur;
+    h->t += 1;
+    h->first = 0;
+    return LB_OK;
+}
+
+template <typename R, typename O>
+lb_status run_output(lb_handle *h, O *ry, O *rb, O *u)
+{
+    HeadPos H = heads(h, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_output<R, O>), dim3((unsigned)h->L.nbm), dim3(TPB), 0, h->stream, h->P, H,
+                       as<R>(h, h->L.mom), ry, rb, u, as<double>(h, h->L.part));
+    return check_launch(h, "k_output");
+}
+
+template <typename R>
+lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype, lb_conserved *cons)
+{
+    const Layout &L = h->L;
+    const long long N = h->P.N;
+    if (lb_status s = run_moments<R>(h, 0)) return s;
+    // outputs: direct to device pointers, or staged in the spare population buffer
+    size_t psz = al(2 * lbq::Q * (size_t)N * sizeof(R));
+    char *stage = h->ws + L.pops + (1 - h->cur) * psz;
+    size_t osz = dtype == 0 ? 8 : 4;
+    void *dry = ry, *drb = rb, *du = u;
+    if (!dst_dev) {
+        dry = ry ? stage : nullptr;
+        drb = rb ? stage + N * osz : nullptr;
+        du = u ? stage + 2 * N * osz : nullptr;
+    }
+    lb_status s = dtype == 0 ? run_output<R, double>(h, (double *)dry, (double *)drb, (double *)du)
+                             : run_output<R, float>(h, (float *)dry, (float *)drb, (float *)du);
+    if (s) return s;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, h->stream, as<double>(h, L.part), as<double>(h, L.cum),
+                       as<double>(h, L.pend), L.nbm, as<double>(h, L.cumc), as<double>(h, L.pendc), NB_SPARSE,
+                       as<double>(h, L.red));
+    if ((s = check_launch(h, "k_reduce"))) return s;
+    double red[16];
+    hipError_t e = hipMemcpyAsync(red, as<double>(h, L.red), 14 * 8, hipMemcpyDeviceToHost, h->stream);
+    if (!dst_dev && e == hipSuccess) {
+        if (ry) e = hipMemcpyAsync(ry, dry, N * osz, hipMemcpyDeviceToHost, h->stream);
+        if (rb && e == hipSuccess) e = hipMemcpyAsync(rb, drb, N * osz, hipMemcpyDeviceToHost, h->stream);
+        if (u && e == hipSuccess) e = hipMemcpyAsync(u, du, 3 * N * osz, hipMemcpyDeviceToHost, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, LB_EDEVICE, std::string("lb_moments copy: ") + hipGetErrorString(e));
+    if (cons) {
+        cons->mass[0] = red[0];
+        cons->mass[1] = red[1];
+        for (int a = 0; a < 3; ++a) cons->mom[a] = red[2 + a];
+        cons->mass_wall[0] = red[5];
+        cons->mass_wall[1] = red[6];
+        cons->mass_open[0] = red[7];
+        cons->mass_open[1] = red[8];
+        cons->mass_created[0] = red[9];
+        cons->mass_created[1] = red[10];
+        cons->mass_deleted[0] = red[11];
+        cons->mass_deleted[1] = red[12];
+    }
+    if (red[13] != 0.0) {
+        h->unstable = 1;
+        return fail(h, LB_EUNSTABLE, "unstable state: NaN, non-positive density or |u| > 0.3");
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_footprint(const lb_params *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(nullptr, LB_EINVAL, "null argument");
+    if (const char *m = validate(*p)) return fail(nullptr, LB_EINVAL, m);
+    *bytes = layout_of(*p).total;
+    return LB_OK;
+}
+
+lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b, const double *u,
+                    void *dev_workspace, size_t ws_bytes, void *hip_stream, lb_handle **out)
+{
+    if (out) *out = nullptr;
+    if (!p || !rho_y || !rho_b || !dev_workspace || !out) return fail(nullptr, LB_EINVAL, "null argument");
+    if (const char *m = validate(*p)) return fail(nullptr, LB_EINVAL, m);
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN) return fail(nullptr, LB_EINVAL, "workspace not 256-byte aligned");
+    Layout L = layout_of(*p);
+    if (ws_bytes < L.total) return fail(nullptr, LB_ENOMEM, "workspace smaller than lb_footprint()");
+    lb_handle *h = new lb_handle();
+    h->p = *p;
+    h->P = make_dev(*p);
+    h->L = L;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->ws = reinterpret_cast<char *>(dev_workspace);
+    h->cur = 0;
+    h->t = 0;
+    h->first = 1;
+    h->unstable = 0;
+    const long long N = h->P.N;
+    const size_t rs = real_size(p->storage);
+    size_t psz = al(2 * lbq::Q * (size_t)N * rs);
+    // stage the initial fields in the second population buffer
+    char *stage = h->ws + L.pops + psz;
+    double *dry = reinterpret_cast<double *>(stage);
+    double *drb = dry + N;
+    double *du = drb + N;
+    hipError_t e = hipMemcpyAsync(dry, rho_y, N * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(drb, rho_b, N * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * 8, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cum, 0, L.pend - L.cum, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cumc, 0, L.pendc - L.cumc, h->stream);
+    if (e != hipSuccess) {
+        std::string m = std::string("lb_create: ") + hipGetErrorString(e);
+        delete h;
+        return fail(nullptr, LB_EDEVICE, m);
+    }
+    HeadPos H = heads(h, nullptr, nullptr, nullptr, nullptr);
+    dim3 grid((unsigned)L.nbm);
+    if (p->storage == LB_F64)
+        hipLaunchKernelGGL(k_init<double>, grid, dim3(TPB), 0, h->stream, h->P, H, dry, drb, du, u ? 1 : 0,
+                           as<double>(h, L.pops));
+    else
+        hipLaunchKernelGGL(k_init<float>, grid, dim3(TPB), 0, h->stream, h->P, H, dry, drb, du, u ? 1 : 0,
+                           as<float>(h, L.pops));
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        std::string m = std::string("lb_create init: ") + hipGetErrorString(e);
+        delete h;
+        return fail(nullptr, LB_EDEVICE, m);
+    }
+    *out = h;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_handle *h, int nsteps)
+{
+    if (!h || nsteps < 0) return fail(h, LB_EINVAL, "bad handle or step count");
+    if (h->unstable) return fail(h, LB_ESTATE, "handle is unstable; only lb_moments and lb_destroy are allowed");
+    for (int n = 0; n < nsteps; ++n) {
+        lb_status s = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
+        if (s) return s;
+        if (h->p.check_interval > 0 && h->t % h->p.check_interval == 0) {
+            lb_conserved c;
+            s = h->p.storage == LB_F64 ? moments_impl<double>(h, nullptr, nullptr, nullptr, 1, 0, &c)
+                                       : moments_impl<float>(h, nullptr, nullptr, nullptr, 1, 0, &c);
+            if (s) return s;
+        }
+    }
+    return LB_OK;
+}
+
+lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype, lb_conserved *cons)
+{
+    if (!h || (dtype != 0 && dtype != 1)) return fail(h, LB_EINVAL, "bad handle or dtype");
+    return h->p.storage == LB_F64 ? moments_impl<double>(h, rho_y, rho_b, u, dst_is_device, dtype, cons)
+                                  : moments_impl<float>(h, rho_y, rho_b, u, dst_is_device, dtype, cons);
+}
+
+long lb_time(const lb_handle *h) { return h ? h->t : -1; }
+
+lb_status lb_destroy(lb_handle *h)
+{
+    if (!h) return LB_EINVAL;
+    delete h;
+    return LB_OK;
+}
+
+const char *lb_strerror(lb_status s)
+{
+    switch (s) {
+    case LB_OK: return "ok";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "workspace too small";
+    case LB_EDEVICE: return "device error";
+    case LB_EUNSTABLE: return "unstable simulation";
+    case LB_ESTATE: return "call not allowed in this state";
+    }
+    return "unknown status";
+}
+
+const char *lb_last_error(const lb_handle *h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
