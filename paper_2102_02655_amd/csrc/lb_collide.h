@@ -29,7 +29,7 @@ struct Grad {
 template <typename R, int I>
 __device__ __forceinline__ void store_one(const DevParams &P, R rY, R rB, R drho, R rho, R vx, R vy, R vz, R vv,
                                           R om, const R (&Pi)[6], R trPi, R pA, R invFF, bool pert, R Fx, R Fy, R Fz,
-                                          R gx, R gy, R gz, R fracY, R rec, R *__restrict__ dT, R *__restrict__ dY,
+                                          R gx, R gy, R gz, double fracY, R rec, R *__restrict__ dT, R *__restrict__ dY,
                                           long long cell, long long N)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
@@ -61,23 +61,25 @@ __device__ __forceinline__ void store_one(const DevParams &P, R rY, R rB, R drho
     }
     const R phiY = R(P.phi[0][SH]), phiB = R(P.phi[1][SH]);
     const R Tst = rY * R(P.phid[0][SH]) + rB * R(P.phid[1][SH]) + drho * wi + rho * E + neq + om2;
-    const R fst = wi * R(P.rho_ref) + Tst;
-    R Yst = fracY * fst;
+    // the ink's share of f*, formed in FP64 so that sum_i f^Y_i = rho_Y holds
+    // to the final rounding of each stored value
+    const double fst = lbq::w(I) * P.rho_ref + (double)Tst;
+    double Yst = fracY * fst;
     if (I > 0) {
         R cg = R(0);
         if (X) cg += X > 0 ? gx : -gx;
         if (Yc) cg += Yc > 0 ? gy : -gy;
         if (Z) cg += Z > 0 ? gz : -gz;
-        Yst += rec * R(lbq::inv_len(I)) * cg * (rY * phiY + rB * phiB);
+        Yst += (double)(rec * R(lbq::inv_len(I)) * cg * (rY * phiY + rB * phiB));
     }
     dT[I * N + cell] = Tst;
-    dY[I * N + cell] = Yst;
+    dY[I * N + cell] = R(Yst);
 }
 
 template <typename R, int I = 0>
 __device__ __forceinline__ void store_all(const DevParams &P, R rY, R rB, R drho, R rho, R vx, R vy, R vz, R vv,
                                           R om, const R (&Pi)[6], R trPi, R pA, R invFF, bool pert, R Fx, R Fy, R Fz,
-                                          R gx, R gy, R gz, R fracY, R rec, R *__restrict__ dT, R *__restrict__ dY,
+                                          R gx, R gy, R gz, double fracY, R rec, R *__restrict__ dT, R *__restrict__ dY,
                                           long long cell, long long N)
 {
     if constexpr (I < lbq::Q) {
@@ -97,9 +99,11 @@ __device__ __forceinline__ void collide_store(const DevParams &P, const Mom<R> &
                                               R &out_rY, R &out_rB, R (&out_u)[3])
 {
     const R cs2 = R(1.0 / 3.0);
-    const R drho = M.m[0], rY = M.m[1];
-    const R rho = R(P.rho_ref) + drho;
-    const R rB = rho - rY;
+    const double rho_d = P.rho_ref + M.dm[0];
+    const double fracY_d = M.dm[1] / rho_d;
+    const R drho = R(M.dm[0]), rY = R(M.dm[1]);
+    const R rho = R(rho_d);
+    const R rB = R(rho_d - M.dm[1]);
     const R irho = R(1) / rho;
     const R ux = M.m[2] * irho, uy = M.m[3] * irho, uz = M.m[4] * irho;
 
@@ -142,21 +146,29 @@ __device__ __forceinline__ void collide_store(const DevParams &P, const Mom<R> &
     const R om = R(1) - R(1) / tau;
 
     // colour-gradient force F_cg = (rho_B/rho) grad(rho_Y/rho) - (rho_Y/rho) grad(rho_B/rho)
-    const R fracY = rY * irho, fracB = rB * irho;
-    const R Fcx = fracB * G.g[3] - fracY * G.g[6];
-    const R Fcy = fracB * G.g[4] - fracY * G.g[7];
-    const R Fcz = fracB * G.g[5] - fracY * G.g[8];
-    const R FF = Fcx * Fcx + Fcy * Fcy + Fcz * Fcz;
+    const R fracY = R(fracY_d), fracB = rB * irho;
+    R Fcx = fracB * G.g[3] - fracY * G.g[6];
+    R Fcy = fracB * G.g[4] - fracY * G.g[7];
+    R Fcz = fracB * G.g[5] - fracY * G.g[8];
+    // only the direction of F_cg enters Omega2: scale by its largest
+    // component so |F|^2 neither underflows nor overflows; below 1e-30 the
+    // operator (proportional to |grad rho^N| ~ |F_cg|) is negligible
+    const R Fmax = fmax(fabs(Fcx), fmax(fabs(Fcy), fabs(Fcz)));
+    const bool pert = Fmax > R(1e-30);
+    const R iF = pert ? R(1) / Fmax : R(0);
+    Fcx *= iF;
+    Fcy *= iF;
+    Fcz *= iF;
+    const R invFF = pert ? R(1) / (Fcx * Fcx + Fcy * Fcy + Fcz * Fcz) : R(0);
     const R gn2 = G.g[0] * G.g[0] + G.g[1] * G.g[1] + G.g[2] * G.g[2];
     const R gn = sqrt(gn2);
-    const bool pert = FF > R(0);
-    const R invFF = pert ? R(1) / FF : R(0);
     const R pA = R(0.5) * R(P.A) * gn;
-    const R inv_geps = R(1) / sqrt(gn2 + R(P.eps2));
+    const R geps2 = gn2 + R(P.eps2);
+    const R inv_geps = geps2 > R(0) ? R(1) / sqrt(geps2) : R(0);
     const R rec = R(P.beta) * fracY * fracB * inv_geps;
 
     store_all<R>(P, rY, rB, drho, rho, vx, vy, vz, vv, om, Pi, trPi, pA, invFF, pert, Fcx, Fcy, Fcz, G.g[0], G.g[1],
-                 G.g[2], fracY, rec, dT, dY, cell, N);
+                 G.g[2], fracY_d, rec, dT, dY, cell, N);
     out_rY = rY;
     out_rB = rB;
     out_u[0] = ux;

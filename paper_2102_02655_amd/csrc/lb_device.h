@@ -12,11 +12,14 @@
 //
 // The per-cell moment set carried from the pull to the collision (the
 // regularised collision needs no more than these, Eq. (reg)):
-//   0 drho = sum T_i           (rho = rho_ref + drho)
-//   1 rhoY = sum Y_i
-//   2..4   j = sum T_i c_i     (total momentum)
-//   5..10  PT = sum T_i c c    (xx, yy, zz, xy, xz, yz)
-//   11..16 PY = sum Y_i c c
+//   dm[0] drho = sum T_i       (rho = rho_ref + drho)        FP64
+//   dm[1] rhoY = sum Y_i                                     FP64
+//   m[2..4]   j = sum T_i c_i  (total momentum)
+//   m[5..10]  PT = sum T_i c c (xx, yy, zz, xy, xz, yz)
+//   m[11..16] PY = sum Y_i c c
+// The two masses are summed and carried in FP64 whatever the storage: in a
+// uniform region every cell rounds alike, so FP32 rounding of a colour's mass
+// (or of rho_Y / rho in the recolouring) would not average out but drift.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +28,8 @@
 
 namespace lbk {
 
-constexpr int NMOM = 17;
+constexpr int NMOM = 17;   // indices of m[]; m[0], m[1] are unused (see dm)
+constexpr int NMOMR = 15;  // moments stored in the storage type: m[2..16]
 constexpr int NCHI = 3;   // rho^N, rho_Y/rho, rho_B/rho
 constexpr int NMAC = 5;   // rho_Y, rho_B, u (bare) for the next pull's boundary rules
 
@@ -146,12 +150,14 @@ __device__ __forceinline__ long long cidx(const DevParams &P, int x, int y, int 
 
 template <typename R>
 struct Mom {
+    double dm[2];
     R m[NMOM];
 };
 
 template <typename R>
 __device__ __forceinline__ void mom_zero(Mom<R> &M)
 {
+    M.dm[0] = M.dm[1] = 0.0;
 #pragma unroll
     for (int q = 0; q < NMOM; ++q) M.m[q] = R(0);
 }
@@ -160,8 +166,8 @@ template <typename R, int I>
 __device__ __forceinline__ void mom_add(Mom<R> &M, R T, R Y)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    M.m[0] += T;
-    M.m[1] += Y;
+    M.dm[0] += (double)T;
+    M.dm[1] += (double)Y;
     if (X) M.m[2] += X > 0 ? T : -T;
     if (Yc) M.m[3] += Yc > 0 ? T : -T;
     if (Z) M.m[4] += Z > 0 ? T : -T;

@@ -73,13 +73,21 @@ __device__ __forceinline__ void cell_xyz(const DevParams &P, long long cell, int
 }
 
 template <typename R>
-__device__ __forceinline__ void write_chi(const DevParams &P, R *chi, long long cell, R rY, R rB)
+__device__ __forceinline__ void write_chi(const DevParams &P, R *chi, long long cell, double rY, double rB)
 {
-    R cN, cY, cB;
-    chi_of<R>(P, rY, rB, cN, cY, cB);
-    chi[cell] = cN;
-    chi[P.N + cell] = cY;
-    chi[2 * P.N + cell] = cB;
+    double cN, cY, cB;
+    chi_of<double>(P, rY, rB, cN, cY, cB);
+    chi[cell] = R(cN);
+    chi[P.N + cell] = R(cY);
+    chi[2 * P.N + cell] = R(cB);
+}
+
+// densities of a fluid cell from its FP64 masses
+__device__ __forceinline__ void dens(const DevParams &P, const double *__restrict__ momd, long long c, double &rY,
+                                    double &rB)
+{
+    rY = momd[P.N + c];
+    rB = P.rho_ref + momd[c] - rY;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -121,8 +129,9 @@ __global__ __launch_bounds__(TPB) void k_init(DevParams P, HeadPos H, const doub
 // values for lb_moments) without touching the cumulative state.
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R *__restrict__ src,
-                                                 const R *__restrict__ mac, R *__restrict__ mom, R *__restrict__ chi,
-                                                 double *__restrict__ slots, int first, int commit)
+                                                 const R *__restrict__ mac, double *__restrict__ momd,
+                                                 R *__restrict__ mom, R *__restrict__ chi, double *__restrict__ slots,
+                                                 int first, int commit)
 {
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
@@ -139,12 +148,14 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R
             Flux fl = {0.0, 0.0, 0.0, 0.0};
             pull_all<R>(P, H, src, mac, x, y, z, cell, near, first != 0, M, fl);
             if (!sc) {
+                momd[cell] = M.dm[0];
+                momd[P.N + cell] = M.dm[1];
 #pragma unroll
-                for (int q = 0; q < NMOM; ++q) mom[q * P.N + cell] = M.m[q];
-                write_chi<R>(P, chi, cell, M.m[1], R(P.rho_ref) + M.m[0] - M.m[1]);
+                for (int q = 2; q < NMOM; ++q) mom[(q - 2) * P.N + cell] = M.m[q];
+                write_chi<R>(P, chi, cell, M.dm[1], P.rho_ref + M.dm[0] - M.dm[1]);
             } else {
-                acc[4] = (double)M.m[1];
-                acc[5] = (double)(R(P.rho_ref) + M.m[0] - M.m[1]);
+                acc[4] = M.dm[1];
+                acc[5] = P.rho_ref + M.dm[0] - M.dm[1];
             }
             acc[0] = fl.wallY;
             acc[1] = fl.wallB;
@@ -167,8 +178,8 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R
 // the moment set and the colour fields are needed downstream.
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0, int by0, int bz0, int bw, int bh,
-                                                int bd, R *__restrict__ mom, R *__restrict__ chi,
-                                                double *__restrict__ slots, int commit)
+                                                int bd, double *__restrict__ momd, R *__restrict__ mom,
+                                                R *__restrict__ chi, double *__restrict__ slots, int commit)
 {
     double acc[2] = {0.0, 0.0};
     const long long total = (long long)bw * bh * bd;
@@ -185,9 +196,8 @@ __global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0,
             if (zz < 0 || zz >= P.nz) continue;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
             if (is_solid(P, H.hx_p, H.hy_p, xx, yy, zz) || is_solid(P, H.hx_c, H.hy_c, xx, yy, zz)) continue;
-            long long nb = cidx(P, xx, yy, zz);
-            double rY = (double)mom[P.N + nb];
-            double rB = (double)(R(P.rho_ref) + mom[nb] - mom[P.N + nb]);
+            double rY, rB;
+            dens(P, momd, cidx(P, xx, yy, zz), rY, rB);
             sY += rY;
             sB += rB;
             ++cnt;
@@ -203,8 +213,10 @@ __global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0,
         double m[NMOM] = {rho - P.rho_ref, rY, rho * vx, rho * vy, 0.0,
                           iso + rho * vx * vx, iso + rho * vy * vy, iso, rho * vx * vy, 0.0, 0.0,
                           rY * (cY2 + vx * vx), rY * (cY2 + vy * vy), rY * cY2, rY * vx * vy, 0.0, 0.0};
-        for (int q = 0; q < NMOM; ++q) mom[q * P.N + cell] = R(m[q]);
-        write_chi<R>(P, chi, cell, R(rY), R(rB));
+        momd[cell] = m[0];
+        momd[P.N + cell] = m[1];
+        for (int q = 2; q < NMOM; ++q) mom[(q - 2) * P.N + cell] = R(m[q]);
+        write_chi<R>(P, chi, cell, rY, rB);
         acc[0] += rY;
         acc[1] += rB;
     }
@@ -215,7 +227,7 @@ __global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0,
 // rho_s^k = zeta^k sum_i w_i s_i rho^k(x + c_i) / sum_i w_i s_i.
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_wall(DevParams P, HeadPos H, int bx0, int by0, int bz0, int bw, int bh,
-                                              int bd, const R *__restrict__ mom, R *__restrict__ chi)
+                                              int bd, const double *__restrict__ momd, R *__restrict__ chi)
 {
     const long long total = (long long)bw * bh * bd;
     for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
@@ -230,17 +242,16 @@ __global__ __launch_bounds__(TPB) void k_wall(DevParams P, HeadPos H, int bx0, i
             if (zz < 0 || zz >= P.nz) continue;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
             if (is_solid(P, H.hx_c, H.hy_c, xx, yy, zz)) continue;
-            long long nb = cidx(P, xx, yy, zz);
             double wi = lbq::w(i);
-            double rY = (double)mom[P.N + nb];
-            double rB = (double)(R(P.rho_ref) + mom[nb] - mom[P.N + nb]);
+            double rY, rB;
+            dens(P, momd, cidx(P, xx, yy, zz), rY, rB);
             nY += wi * rY;
             nB += wi * rB;
             den += wi;
         }
         long long cell = cidx(P, x, y, z);
-        R sY = den > 0.0 ? R(P.zeta_noz[0] * nY / den) : R(0);
-        R sB = den > 0.0 ? R(P.zeta_noz[1] * nB / den) : R(0);
+        double sY = den > 0.0 ? P.zeta_noz[0] * nY / den : 0.0;
+        double sB = den > 0.0 ? P.zeta_noz[1] * nB / den : 0.0;
         write_chi<R>(P, chi, cell, sY, sB);
     }
 }
@@ -250,7 +261,7 @@ __global__ __launch_bounds__(TPB) void k_wall(DevParams P, HeadPos H, int bx0, i
 // layer, pressure faces their imposed densities, the inlet lid pure ink, the
 // head's shell columns above the top the nozzle's fictitious densities.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const R *__restrict__ mom,
+__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const double *__restrict__ momd,
                                                R *__restrict__ ghost)
 {
     long long plane = (long long)P.nx * P.ny;
@@ -290,20 +301,21 @@ __global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const R *
             if (zg + lbq::cz(i) != zin) continue;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
             if (is_solid(P, H.hx_c, H.hy_c, xx, yy, zin)) continue;
-            long long nb = cidx(P, xx, yy, zin);
             double wi = lbq::w(i);
-            nY += wi * (double)mom[P.N + nb];
-            nB += wi * (double)(R(P.rho_ref) + mom[nb] - mom[P.N + nb]);
+            double nrY, nrB;
+            dens(P, momd, cidx(P, xx, yy, zin), nrY, nrB);
+            nY += wi * nrY;
+            nB += wi * nrB;
             den += wi;
         }
         rY = den > 0.0 ? z0 * nY / den : 0.0;
         rB = den > 0.0 ? z1 * nB / den : 0.0;
     }
-    R cN, cY, cB;
-    chi_of<R>(P, R(rY), R(rB), cN, cY, cB);
-    ghost[(face * 3 + 0) * plane + c] = cN;
-    ghost[(face * 3 + 1) * plane + c] = cY;
-    ghost[(face * 3 + 2) * plane + c] = cB;
+    double cN, cY, cB;
+    chi_of<double>(P, rY, rB, cN, cY, cB);
+    ghost[(face * 3 + 0) * plane + c] = R(cN);
+    ghost[(face * 3 + 1) * plane + c] = R(cY);
+    ghost[(face * 3 + 2) * plane + c] = R(cB);
 }
 
 template <typename R>
@@ -361,9 +373,9 @@ __device__ __forceinline__ void grad_pairs(const DevParams &P, const R *__restri
 }
 
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_collide(DevParams P, HeadPos H, const R *__restrict__ mom,
-                                                 const R *__restrict__ chi, const R *__restrict__ ghost,
-                                                 R *__restrict__ dst, R *__restrict__ mac)
+__global__ __launch_bounds__(TPB) void k_collide(DevParams P, HeadPos H, const double *__restrict__ momd,
+                                                 const R *__restrict__ mom, const R *__restrict__ chi,
+                                                 const R *__restrict__ ghost, R *__restrict__ dst, R *__restrict__ mac)
 {
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     if (cell >= P.N) return;
@@ -372,8 +384,10 @@ __global__ __launch_bounds__(TPB) void k_collide(DevParams P, HeadPos H, const R
     bool near = !far_from_head(P, H.hx_c, H.hy_c, x, y);
     if (near && is_solid(P, H.hx_c, H.hy_c, x, y, z)) return;
     Mom<R> M;
+    M.dm[0] = momd[cell];
+    M.dm[1] = momd[P.N + cell];
 #pragma unroll
-    for (int q = 0; q < NMOM; ++q) M.m[q] = mom[q * P.N + cell];
+    for (int q = 2; q < NMOM; ++q) M.m[q] = mom[(q - 2) * P.N + cell];
     Grad<R> G;
 #pragma unroll
     for (int q = 0; q < 9; ++q) G.g[q] = R(0);
@@ -390,9 +404,9 @@ __global__ __launch_bounds__(TPB) void k_collide(DevParams P, HeadPos H, const R
 // Fields for lb_moments: rho_Y, rho_B, physical velocity (j + F/2)/rho; block
 // sums of mass and momentum; instability flag.
 template <typename R, typename O>
-__global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const R *__restrict__ mom,
-                                                O *__restrict__ ory, O *__restrict__ orb, O *__restrict__ ou,
-                                                double *__restrict__ part)
+__global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const double *__restrict__ momd,
+                                                const R *__restrict__ mom, O *__restrict__ ory, O *__restrict__ orb,
+                                                O *__restrict__ ou, double *__restrict__ part)
 {
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NPART] = {0, 0, 0, 0, 0, 0};
@@ -402,12 +416,9 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const R 
         bool solid = !far_from_head(P, H.hx_c, H.hy_c, x, y) && is_solid(P, H.hx_c, H.hy_c, x, y, z);
         double rY = 0.0, rB = 0.0, U[3] = {0.0, 0.0, 0.0};
         if (!solid) {
-            R drho = mom[cell], rYr = mom[P.N + cell];
-            R rho = R(P.rho_ref) + drho;
-            rY = (double)rYr;
-            rB = (double)(rho - rYr);
-            double r = (double)rho;
-            double j[3] = {(double)mom[2 * P.N + cell], (double)mom[3 * P.N + cell], (double)mom[4 * P.N + cell]};
+            dens(P, momd, cell, rY, rB);
+            double r = rY + rB;
+            double j[3] = {(double)mom[cell], (double)mom[P.N + cell], (double)mom[2 * P.N + cell]};
             double F[3];
             for (int a = 0; a < 3; ++a) F[a] = r * P.g[a];
             if (P.drag_gamma != 0.0 && P.face_lo == FACE_WALL && (double)z + 0.5 < P.drag_range)
@@ -483,7 +494,7 @@ constexpr size_t ALIGN = 256;
 size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-    size_t pops, mom, chi, ghost, mac, cum, pend, part, cumc, pendc, red, total;
+    size_t pops, momd, mom, chi, ghost, mac, cum, pend, part, cumc, pendc, red, total;
     long long nbm;
 };
 
@@ -498,8 +509,10 @@ Layout layout_of(const lb_params &p)
     size_t off = 0;
     L.pops = off;
     off += 2 * al(2 * lbq::Q * (size_t)N * rs);
+    L.momd = off;
+    off += al(2 * (size_t)N * 8);
     L.mom = off;
-    off += al(NMOM * (size_t)N * rs);
+    off += al(NMOMR * (size_t)N * rs);
     L.chi = off;
     off += al(NCHI * (size_t)N * rs);
     L.ghost = off;
@@ -739,12 +752,13 @@ lb_status run_moments(lb_handle *h, int commit)
     R *src = as<R>(h, L.pops + h->cur * al(2 * lbq::Q * (size_t)h->P.N * sizeof(R)));
     double *slots = as<double>(h, commit ? L.cum : L.pend);
     hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, src, as<R>(h, L.mac),
-                       as<R>(h, L.mom), as<R>(h, L.chi), slots, h->first, commit);
+                       as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), slots, h->first, commit);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
         Box b = head_box(h, xl, xh, yl, yh);
         hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h,
-                           b.d, as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, commit ? L.cumc : L.pendc), commit);
+                           b.d, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                           as<double>(h, commit ? L.cumc : L.pendc), commit);
         if (lb_status s = check_launch(h, "k_create")) return s;
     } else if (!commit) {
         if (hipMemsetAsync(as<double>(h, L.pendc), 0, NB_SPARSE * 2 * 8, h->stream) != hipSuccess)
@@ -765,18 +779,19 @@ lb_status run_step(lb_handle *h)
         long long tot = (long long)b.w * b.h * b.d;
         unsigned nb = (unsigned)std::min<long long>((tot + TPB - 1) / TPB, 4096);
         hipLaunchKernelGGL(k_wall<R>, dim3(nb), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h, b.d,
-                           as<R>(h, L.mom), as<R>(h, L.chi));
+                           as<double>(h, L.momd), as<R>(h, L.chi));
         if (lb_status s = check_launch(h, "k_wall")) return s;
     }
     if (!h->P.periodic_z) {
         long long n = 2LL * h->p.nx * h->p.ny;
         hipLaunchKernelGGL(k_ghost<R>, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, h->stream, h->P, H,
-                           as<R>(h, L.mom), as<R>(h, L.ghost));
+                           as<double>(h, L.momd), as<R>(h, L.ghost));
         if (lb_status s = check_launch(h, "k_ghost")) return s;
     }
     size_t psz = al(2 * lbq::Q * (size_t)h->P.N * sizeof(R));
     R *dst = as<R>(h, L.pops + (1 - h->cur) * psz);
-    hipLaunchKernelGGL(k_collide<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, as<R>(h, L.mom),
+    hipLaunchKernelGGL(k_collide<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H,
+                       as<double>(h, L.momd), as<R>(h, L.mom),
                        as<R>(h, L.chi), as<R>(h, L.ghost), dst, as<R>(h, L.mac));
     if (lb_status s = check_launch(h, "k_collide")) return s;
     h->cur = 1 - h->cur;
@@ -790,7 +805,7 @@ lb_status run_output(lb_handle *h, O *ry, O *rb, O *u)
 {
     HeadPos H = heads(h, nullptr, nullptr, nullptr, nullptr);
     hipLaunchKernelGGL((k_output<R, O>), dim3((unsigned)h->L.nbm), dim3(TPB), 0, h->stream, h->P, H,
-                       as<R>(h, h->L.mom), ry, rb, u, as<double>(h, h->L.part));
+                       as<double>(h, h->L.momd), as<R>(h, h->L.mom), ry, rb, u, as<double>(h, h->L.part));
     return check_launch(h, "k_output");
 }
 

@@ -82,6 +82,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_2102_02655_amd/build.py)")
+        # Load PyTorch's HIP runtime first: the library then binds to that same
+        # runtime (same soname), so torch's device memory and streams are
+        # valid in its calls.  Loading the library first would bring in a
+        # second runtime instance.
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.lb_footprint.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
