@@ -26,86 +26,142 @@ struct Grad {
     R g[9];
 };
 
+// Per-cell coefficients of the post-collision total.  On D3Q19 every term of
+// f*_i is a quadratic form in c_i times w_i, plus a rest-link correction:
+//   f*_i - w_i rho_ref = w_i [ k1 + a.c_i + c_i.Bm.c_i ]                (i > 0)
+//   f*_0 - w_0 rho_ref = t0                                             (i = 0)
+// with, for u' = u + F/rho (exact-difference method), omega = 1 - 1/tau,
+// the unit colour-gradient direction n and p = (A/2) |grad rho^N|:
+//   a  = 3 rho u'
+//   Bm = 4.5 rho u'u' + 4.5 omega Pi^neq + p (n n - I)
+//   a0 = -1.5 rho u'^2 - 1.5 omega tr Pi^neq + (2/3) p
+//   k1 = a0 + drho + sum_k rho_k (phi_i^k - w_i) / w_i
+//   t0 = w_0 (a0 + drho) + sum_k rho_k (phi_0^k - w_0)
+// which is the regularised BGK of Eq. (reg)/(modbgk) with the equilibrium's
+// rest-frame weights, plus Omega2 of Eq. (pertopform) with
+// B_i = w_i (|c_i|^2 - 2/3).  The ink share is
+//   f^Y_i = (rho_Y/rho) f*_i + w_i (beta rho_Y rho_B / rho^2) e (c_i.n_eps)/|c_i|
+// with sum_k rho_k phi_i^k = w_i e on the moving links.
+template <typename R>
+struct OutCoef {
+    R k1, t0, ax, ay, az, bxx, byy, bzz, bxy, bxz, byz;
+    R rx, ry, rz;  // w-free recolouring vector: rec * e * grad rho^N
+    double fracY;
+};
+
 template <typename R, int I>
-__device__ __forceinline__ void store_one(const DevParams &P, R rY, R rB, R drho, R rho, R vx, R vy, R vz, R vv,
-                                          R om, const R (&Pi)[6], R trPi, R pA, R invFF, bool pert, R Fx, R Fy, R Fz,
-                                          R gx, R gy, R gz, double fracY, R rec, R *__restrict__ dT, R *__restrict__ dY,
-                                          long long cell, long long N)
+__device__ __forceinline__ void store_one(const DevParams &P, const OutCoef<R> &K, R *__restrict__ dT,
+                                          R *__restrict__ dY, unsigned cell, long long N)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    constexpr int SH = lbq::shell(I);
-    const R wi = R(lbq::w(I));
-    // c.v, c.Pi.c
-    R cv = R(0);
-    if (X) cv += X > 0 ? vx : -vx;
-    if (Yc) cv += Yc > 0 ? vy : -vy;
-    if (Z) cv += Z > 0 ? vz : -vz;
-    R cPc = R(0);
-    if (X) cPc += Pi[0];
-    if (Yc) cPc += Pi[1];
-    if (Z) cPc += Pi[2];
-    if (X && Yc) cPc += (X * Yc > 0 ? R(2) : R(-2)) * Pi[3];
-    if (X && Z) cPc += (X * Z > 0 ? R(2) : R(-2)) * Pi[4];
-    if (Yc && Z) cPc += (Yc * Z > 0 ? R(2) : R(-2)) * Pi[5];
-    const R E = wi * (R(3) * cv + R(4.5) * cv * cv - R(1.5) * vv);
-    const R neq = om * wi * R(4.5) * (cPc - R(1.0 / 3.0) * trPi);
-    R om2 = R(0);
-    if (I > 0) {
-        R Fc = R(0);
-        if (X) Fc += X > 0 ? Fx : -Fx;
-        if (Yc) Fc += Yc > 0 ? Fy : -Fy;
-        if (Z) Fc += Z > 0 ? Fz : -Fz;
-        om2 = pert ? pA * (wi * Fc * Fc * invFF - R(lbq::B_of_shell(SH))) : R(0);
+    R Tst;
+    double Yst;
+    if constexpr (I == 0) {
+        Tst = K.t0;
+        Yst = K.fracY * (lbq::w(0) * P.rho_ref + (double)Tst);
     } else {
-        om2 = pert ? -pA * R(lbq::B_of_shell(0)) : R(0);
-    }
-    const R phiY = R(P.phi[0][SH]), phiB = R(P.phi[1][SH]);
-    const R Tst = rY * R(P.phid[0][SH]) + rB * R(P.phid[1][SH]) + drho * wi + rho * E + neq + om2;
-    // the ink's share of f*, formed in FP64 so that sum_i f^Y_i = rho_Y holds
-    // to the final rounding of each stored value
-    const double fst = lbq::w(I) * P.rho_ref + (double)Tst;
-    double Yst = fracY * fst;
-    if (I > 0) {
+        R q = K.k1;
+        if (X) q += X > 0 ? K.ax : -K.ax;
+        if (Yc) q += Yc > 0 ? K.ay : -K.ay;
+        if (Z) q += Z > 0 ? K.az : -K.az;
+        if (X) q += K.bxx;
+        if (Yc) q += K.byy;
+        if (Z) q += K.bzz;
+        if (X && Yc) q += X * Yc > 0 ? K.bxy : -K.bxy;
+        if (X && Z) q += X * Z > 0 ? K.bxz : -K.bxz;
+        if (Yc && Z) q += Yc * Z > 0 ? K.byz : -K.byz;
+        const R wi = R(lbq::w(I));
+        Tst = wi * q;
         R cg = R(0);
-        if (X) cg += X > 0 ? gx : -gx;
-        if (Yc) cg += Yc > 0 ? gy : -gy;
-        if (Z) cg += Z > 0 ? gz : -gz;
-        Yst += (double)(rec * R(lbq::inv_len(I)) * cg * (rY * phiY + rB * phiB));
+        if (X) cg += X > 0 ? K.rx : -K.rx;
+        if (Yc) cg += Yc > 0 ? K.ry : -K.ry;
+        if (Z) cg += Z > 0 ? K.rz : -K.rz;
+        // the ink's share, formed in FP64 so that sum_i f^Y_i = rho_Y holds to
+        // the final rounding of each stored value
+        Yst = K.fracY * (lbq::w(I) * P.rho_ref + (double)Tst) + (double)(wi * R(lbq::inv_len(I)) * cg);
     }
-    dT[I * N + cell] = Tst;
-    dY[I * N + cell] = R(Yst);
+    (dT + (long long)I * N)[cell] = Tst;
+    (dY + (long long)I * N)[cell] = R(Yst);
 }
 
 template <typename R, int I = 0>
-__device__ __forceinline__ void store_all(const DevParams &P, R rY, R rB, R drho, R rho, R vx, R vy, R vz, R vv,
-                                          R om, const R (&Pi)[6], R trPi, R pA, R invFF, bool pert, R Fx, R Fy, R Fz,
-                                          R gx, R gy, R gz, double fracY, R rec, R *__restrict__ dT, R *__restrict__ dY,
-                                          long long cell, long long N)
+__device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &K, R *__restrict__ dT,
+                                          R *__restrict__ dY, unsigned cell, long long N)
 {
     if constexpr (I < lbq::Q) {
-        store_one<R, I>(P, rY, rB, drho, rho, vx, vy, vz, vv, om, Pi, trPi, pA, invFF, pert, Fx, Fy, Fz, gx, gy, gz,
-                        fracY, rec, dT, dY, cell, N);
-        store_all<R, I + 1>(P, rY, rB, drho, rho, vx, vy, vz, vv, om, Pi, trPi, pA, invFF, pert, Fx, Fy, Fz, gx, gy,
-                            gz, fracY, rec, dT, dY, cell, N);
+        store_one<R, I>(P, K, dT, dY, cell, N);
+        store_all<R, I + 1>(P, K, dT, dY, cell, N);
     }
 }
 
-// Collide one fluid cell from its moment set and colour gradients; store the
-// 38 post-collision values at the cell (the next step pulls them) and return
-// rho_Y, rho_B and the bare velocity for the boundary rules of the next pull.
+// What the collision needs of a cell, derived from its moment set: the two
+// masses (FP64), momentum, the total non-equilibrium stress and the BGK
+// factor 1 - 1/tau of the local mixture relaxation time.
 template <typename R>
-__device__ __forceinline__ void collide_store(const DevParams &P, const Mom<R> &M, const Grad<R> &G, int z,
-                                              R *__restrict__ dT, R *__restrict__ dY, long long cell, long long N,
-                                              R &out_rY, R &out_rB, R (&out_u)[3])
+struct CellState {
+    double drho, rY;
+    R j[3];
+    R Pi[6];
+    R om;
+};
+
+template <typename R>
+__device__ __forceinline__ CellState<R> cell_state(const DevParams &P, const Mom<R> &M)
 {
+    CellState<R> C;
     const R cs2 = R(1.0 / 3.0);
+    C.drho = M.dm[0];
+    C.rY = M.dm[1];
     const double rho_d = P.rho_ref + M.dm[0];
-    const double fracY_d = M.dm[1] / rho_d;
     const R drho = R(M.dm[0]), rY = R(M.dm[1]);
     const R rho = R(rho_d);
     const R rB = R(rho_d - M.dm[1]);
     const R irho = R(1) / rho;
     const R ux = M.m[2] * irho, uy = M.m[3] * irho, uz = M.m[4] * irho;
+    C.j[0] = M.m[2];
+    C.j[1] = M.m[3];
+    C.j[2] = M.m[4];
+    // non-equilibrium stresses: total (collision) and ink (strain rate)
+    const R iso = rY * R(P.dcs2[0]) + rB * R(P.dcs2[1]) + drho * cs2;
+    C.Pi[0] = M.m[5] - iso - rho * ux * ux;
+    C.Pi[1] = M.m[6] - iso - rho * uy * uy;
+    C.Pi[2] = M.m[7] - iso - rho * uz * uz;
+    C.Pi[3] = M.m[8] - rho * ux * uy;
+    C.Pi[4] = M.m[9] - rho * ux * uz;
+    C.Pi[5] = M.m[10] - rho * uy * uz;
+    const R cY2 = cs2 + R(P.dcs2[0]);
+    const R Yxx = M.m[11] - rY * (cY2 + ux * ux);
+    const R Yyy = M.m[12] - rY * (cY2 + uy * uy);
+    const R Yzz = M.m[13] - rY * (cY2 + uz * uz);
+    const R Yxy = M.m[14] - rY * ux * uy;
+    const R Yxz = M.m[15] - rY * ux * uz;
+    const R Yyz = M.m[16] - rY * uy * uz;
+    const R S = sqrt(Yxx * Yxx + Yyy * Yyy + Yzz * Yzz + R(2) * (Yxy * Yxy + Yxz * Yxz + Yyz * Yyz));
+    // local relaxation time: ink from its strain rate, air Newtonian, mixed
+    // harmonically in the viscosity (Eq. (tauinter))
+    const R tauY = tau_ink<R>(P, S, rY);
+    const R nuY = cs2 * (tauY - R(0.5)), nuB = cs2 * (R(P.tau_b) - R(0.5));
+    const R inv_nu = (rY * irho) / nuY + (rB * irho) / nuB;
+    const R tau = R(0.5) + R(3) / inv_nu;
+    C.om = R(1) - R(1) / tau;
+    return C;
+}
+
+// Collide one fluid cell from its state and colour gradients; store the 38
+// post-collision values at the cell (the next step pulls them) and return
+// rho_Y, rho_B and the bare velocity for the boundary rules of the next pull.
+template <typename R>
+__device__ __forceinline__ void collide_state(const DevParams &P, const CellState<R> &C, const Grad<R> &G, int z,
+                                              R *__restrict__ dT, R *__restrict__ dY, long long cell, long long N,
+                                              R &out_rY, R &out_rB, R (&out_u)[3])
+{
+    const double rho_d = P.rho_ref + C.drho;
+    const double fracY_d = C.rY / rho_d;
+    const R drho = R(C.drho), rY = R(C.rY);
+    const R rho = R(rho_d);
+    const R rB = R(rho_d - C.rY);
+    const R irho = R(1) / rho;
+    const R ux = C.j[0] * irho, uy = C.j[1] * irho, uz = C.j[2] * irho;
 
     // force: body force and the substrate drag (exact-difference method)
     R Fx = rho * R(P.g[0]), Fy = rho * R(P.g[1]), Fz = rho * R(P.g[2]);
@@ -116,34 +172,8 @@ __device__ __forceinline__ void collide_store(const DevParams &P, const Mom<R> &
         Fz -= gam * (uz - R(P.u_lo[2]));
     }
     const R vx = ux + Fx * irho, vy = uy + Fy * irho, vz = uz + Fz * irho;
-    const R vv = vx * vx + vy * vy + vz * vz;
-
-    // non-equilibrium stresses: total (collision) and ink (strain rate)
-    const R iso = rY * R(P.dcs2[0]) + rB * R(P.dcs2[1]) + drho * cs2;
-    R Pi[6];
-    Pi[0] = M.m[5] - iso - rho * ux * ux;
-    Pi[1] = M.m[6] - iso - rho * uy * uy;
-    Pi[2] = M.m[7] - iso - rho * uz * uz;
-    Pi[3] = M.m[8] - rho * ux * uy;
-    Pi[4] = M.m[9] - rho * ux * uz;
-    Pi[5] = M.m[10] - rho * uy * uz;
-    const R trPi = Pi[0] + Pi[1] + Pi[2];
-    const R cY2 = cs2 + R(P.dcs2[0]);
-    const R Yxx = M.m[11] - rY * (cY2 + ux * ux);
-    const R Yyy = M.m[12] - rY * (cY2 + uy * uy);
-    const R Yzz = M.m[13] - rY * (cY2 + uz * uz);
-    const R Yxy = M.m[14] - rY * ux * uy;
-    const R Yxz = M.m[15] - rY * ux * uz;
-    const R Yyz = M.m[16] - rY * uy * uz;
-    const R S = sqrt(Yxx * Yxx + Yyy * Yyy + Yzz * Yzz + R(2) * (Yxy * Yxy + Yxz * Yxz + Yyz * Yyz));
-
-    // local relaxation time: ink from its strain rate, air Newtonian, mixed
-    // harmonically in the viscosity (Eq. (tauinter))
-    const R tauY = tau_ink<R>(P, S, rY);
-    const R nuY = cs2 * (tauY - R(0.5)), nuB = cs2 * (R(P.tau_b) - R(0.5));
-    const R inv_nu = (rY * irho) / nuY + (rB * irho) / nuB;
-    const R tau = R(0.5) + R(3) / inv_nu;
-    const R om = R(1) - R(1) / tau;
+    const R trPi = C.Pi[0] + C.Pi[1] + C.Pi[2];
+    const R om = C.om;
 
     // colour-gradient force F_cg = (rho_B/rho) grad(rho_Y/rho) - (rho_Y/rho) grad(rho_B/rho)
     const R fracY = R(fracY_d), fracB = rB * irho;
@@ -161,14 +191,36 @@ __device__ __forceinline__ void collide_store(const DevParams &P, const Mom<R> &
     Fcz *= iF;
     const R invFF = pert ? R(1) / (Fcx * Fcx + Fcy * Fcy + Fcz * Fcz) : R(0);
     const R gn2 = G.g[0] * G.g[0] + G.g[1] * G.g[1] + G.g[2] * G.g[2];
-    const R gn = sqrt(gn2);
-    const R pA = R(0.5) * R(P.A) * gn;
+    const R pA = pert ? R(0.5) * R(P.A) * sqrt(gn2) : R(0);
     const R geps2 = gn2 + R(P.eps2);
     const R inv_geps = geps2 > R(0) ? R(1) / sqrt(geps2) : R(0);
-    const R rec = R(P.beta) * fracY * fracB * inv_geps;
+    const R pn = pA * invFF;
 
-    store_all<R>(P, rY, rB, drho, rho, vx, vy, vz, vv, om, Pi, trPi, pA, invFF, pert, Fcx, Fcy, Fcz, G.g[0], G.g[1],
-                 G.g[2], fracY_d, rec, dT, dY, cell, N);
+    OutCoef<R> K;
+    const R h = R(4.5);
+    K.ax = R(3) * rho * vx;
+    K.ay = R(3) * rho * vy;
+    K.az = R(3) * rho * vz;
+    K.bxx = h * (rho * vx * vx + om * C.Pi[0]) + pn * Fcx * Fcx - pA;
+    K.byy = h * (rho * vy * vy + om * C.Pi[1]) + pn * Fcy * Fcy - pA;
+    K.bzz = h * (rho * vz * vz + om * C.Pi[2]) + pn * Fcz * Fcz - pA;
+    K.bxy = R(2) * (h * (rho * vx * vy + om * C.Pi[3]) + pn * Fcx * Fcy);
+    K.bxz = R(2) * (h * (rho * vx * vz + om * C.Pi[4]) + pn * Fcx * Fcz);
+    K.byz = R(2) * (h * (rho * vy * vz + om * C.Pi[5]) + pn * Fcy * Fcz);
+    const R a0 = R(-1.5) * (rho * (vx * vx + vy * vy + vz * vz) + om * trPi) + R(2.0 / 3.0) * pA;
+    // rest-frame weights relative to w: phi_i^k - w_i = w_i kappa_k (i > 0)
+    const R kapY = R(P.phid[0][1] / lbq::w(1)), kapB = R(P.phid[1][1] / lbq::w(1));
+    K.k1 = a0 + drho + rY * kapY + rB * kapB;
+    K.t0 = R(lbq::w(0)) * (a0 + drho) + rY * R(P.phid[0][0]) + rB * R(P.phid[1][0]);
+    // recolouring: beta rho_Y rho_B / rho^2 * e / |grad rho^N|_eps * grad rho^N,
+    // e = sum_k rho_k (1 - alpha_k) / (1 - w_0)
+    const R e = rY * R(P.phi[0][1] / lbq::w(1)) + rB * R(P.phi[1][1] / lbq::w(1));
+    const R rec = R(P.beta) * fracY * fracB * inv_geps * e;
+    K.rx = rec * G.g[0];
+    K.ry = rec * G.g[1];
+    K.rz = rec * G.g[2];
+    K.fracY = fracY_d;
+    store_all<R>(P, K, dT, dY, (unsigned)cell, N);
     out_rY = rY;
     out_rB = rB;
     out_u[0] = ux;

@@ -162,12 +162,15 @@ __device__ __forceinline__ void mom_zero(Mom<R> &M)
     for (int q = 0; q < NMOM; ++q) M.m[q] = R(0);
 }
 
-template <typename R, int I>
+// Accumulate one pulled population pair.  FULL = false keeps only the two
+// masses (cells whose density feeds a neighbour's colour gradient).
+template <typename R, int I, bool FULL = true>
 __device__ __forceinline__ void mom_add(Mom<R> &M, R T, R Y)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
     M.dm[0] += (double)T;
     M.dm[1] += (double)Y;
+    if constexpr (!FULL) return;
     if (X) M.m[2] += X > 0 ? T : -T;
     if (Yc) M.m[3] += Yc > 0 ? T : -T;
     if (Z) M.m[4] += Z > 0 ? T : -T;
@@ -197,7 +200,7 @@ struct Flux {
 // (Sec. II.B: halfway bounce-back, Eq. (movwall) with the wall density
 // extrapolated inward, Eq. (movnozzle) on the lid, anti-bounce-back on
 // pressure faces).
-template <typename R, int I>
+template <typename R, int I, bool FULL = true>
 __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
                                          const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
                                          bool first, Mom<R> &M, Flux &fl)
@@ -208,7 +211,7 @@ __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, c
     const R *sT = src;
     const R *sY = src + (long long)lbq::Q * N;
     if (first) {
-        mom_add<R, I>(M, sT[I * N + cell], sY[I * N + cell]);
+        mom_add<R, I, FULL>(M, sT[I * N + cell], sY[I * N + cell]);
         return;
     }
     int xs = X ? wrap(x - X, P.nx) : x;
@@ -217,7 +220,7 @@ __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, c
     int st = (Z == 0 && !near) ? ST_FLUID : classify(P, H.hx_p, H.hy_p, xs, ys, zs, near);
     if (st == ST_FLUID) {
         long long sc = ((long long)zs * P.ny + ys) * P.nx + xs;
-        mom_add<R, I>(M, sT[I * N + sc], sY[I * N + sc]);
+        mom_add<R, I, FULL>(M, sT[I * N + sc], sY[I * N + sc]);
         return;
     }
     // the link from x towards the wall is IB; its post-collision values
@@ -309,18 +312,78 @@ __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, c
     fl.openB += open ? dB : 0.0;
     fl.wallY += open ? 0.0 : dY;
     fl.wallB += open ? 0.0 : dB;
-    mom_add<R, I>(M, T, Yv);
+    mom_add<R, I, FULL>(M, T, Yv);
 }
 
-template <typename R, int I = 0>
+template <typename R, bool FULL = true, int I = 0>
 __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
                                          const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
                                          bool first, Mom<R> &M, Flux &fl)
 {
     if constexpr (I < lbq::Q) {
-        pull_one<R, I>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
-        pull_all<R, I + 1>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
+        pull_one<R, I, FULL>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
+        pull_all<R, FULL, I + 1>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
     }
+}
+
+// Pull of a cell none of whose links touches a boundary (all 18 sources are
+// fluid at t-1): plain shifted loads, x and y periodic, z periodic or inside.
+// Source offsets are 32-bit (the population plane base is a scalar), so each
+// load needs one address register.
+struct BulkIdx {
+    unsigned xo[3], yo[3], zo[3];  // offsets of x-1..x+1, rows y-1..y+1, planes z-1..z+1
+};
+
+__device__ __forceinline__ BulkIdx bulk_index(const DevParams &P, int x, int y, int z)
+{
+    BulkIdx b;
+    const unsigned nx = (unsigned)P.nx, plane = (unsigned)P.nx * (unsigned)P.ny;
+#pragma unroll
+    for (int d = -1; d <= 1; ++d) {
+        b.xo[d + 1] = (unsigned)wrap(x + d, P.nx);
+        b.yo[d + 1] = (unsigned)wrap(y + d, P.ny) * nx;
+        b.zo[d + 1] = (unsigned)wrap(z + d, P.nz) * plane;
+    }
+    return b;
+}
+
+// mom_add over all links of loaded values
+template <typename R, bool FULL, int I = 0>
+__device__ __forceinline__ void mom_add_all(Mom<R> &M, const R (&vT)[lbq::Q], const R (&vY)[lbq::Q])
+{
+    if constexpr (I < lbq::Q) {
+        mom_add<R, I, FULL>(M, vT[I], vY[I]);
+        mom_add_all<R, FULL, I + 1>(M, vT, vY);
+    }
+}
+
+// The 38 loads of a bulk pull (issued together, used later: the march keeps
+// them in flight across another plane's collision).
+template <typename R>
+__device__ __forceinline__ void pull_bulk_issue(const DevParams &P, const R *__restrict__ src, const BulkIdx &B,
+                                                unsigned cell, bool first, R (&vT)[lbq::Q], R (&vY)[lbq::Q])
+{
+    const long long N = P.N;
+#pragma unroll
+    for (int I = 0; I < lbq::Q; ++I) {
+        // 32-bit cell offset into the population's plane (a scalar base)
+        const unsigned sc = first ? cell : B.zo[1 - lbq::cz(I)] + B.yo[1 - lbq::cy(I)] + B.xo[1 - lbq::cx(I)];
+        vT[I] = (src + (long long)I * N)[sc];
+        vY[I] = (src + (long long)(lbq::Q + I) * N)[sc];
+    }
+}
+
+// All 38 loads are issued before any is used (a scheduling barrier keeps the
+// compiler from interleaving them with the sums), so a cell costs one memory
+// round trip.
+template <typename R, bool FULL>
+__device__ __forceinline__ void pull_bulk(const DevParams &P, const R *__restrict__ src, const BulkIdx &B,
+                                          unsigned cell, bool first, Mom<R> &M)
+{
+    R vT[lbq::Q], vY[lbq::Q];
+    pull_bulk_issue<R>(P, src, B, cell, first, vT, vY);
+    __builtin_amdgcn_sched_barrier(0);
+    mom_add_all<R, FULL>(M, vT, vY);
 }
 
 // Colour fields of a site from its densities: rho^N (the standard phase field
@@ -331,9 +394,11 @@ __device__ __forceinline__ void chi_of(const DevParams &P, R rY, R rB, R &cN, R 
 {
     R a = rY * R(1.0 / P.rho0[0]), b = rB * R(1.0 / P.rho0[1]);
     R s = a + b, t = rY + rB;
-    cN = s != R(0) ? (a - b) / s : R(0);
-    cY = t != R(0) ? rY / t : R(0);
-    cB = t != R(0) ? rB / t : R(0);
+    const R is = s != R(0) ? R(1) / s : R(0);
+    const R it = t != R(0) ? R(1) / t : R(0);
+    cN = (a - b) * is;
+    cY = rY * it;
+    cB = rB * it;
 }
 
 // ----------------------------------------------------------- rheology

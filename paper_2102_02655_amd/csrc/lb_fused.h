@@ -1,0 +1,274 @@
+// lb_fused.h -- the single-pass time step: pull, moments, colour stencil,
+// collision and store in one kernel.
+//
+// The colour gradient of a cell (Eq. (lattgrad)) needs the post-stream
+// densities of its 18 neighbours at the same time level, i.e. the pulled
+// populations of the neighbours.  A workgroup therefore owns a 64 x TY tile of
+// columns and marches up a chunk of z planes, one thread per column of the
+// tile or of its one-cell ring.  Iteration p:
+//   1. issue the 38 loads that pull the thread's cell of plane p;
+//   2. collide the tile cell of plane p - 2 from its parked state and the LDS
+//      colour stencil (planes p - 3 .. p - 1), store its 38 values
+//      (this arithmetic covers the latency of the loads of step 1);
+//   3. reduce the loaded populations: colour fields into a 4-plane LDS ring,
+//      and for tile cells the state the collision needs (masses, momentum,
+//      the non-equilibrium stress, the BGK factor of the local relaxation
+//      time -- the regularised collision needs nothing else, Eq. (reg)) into
+//      a 2-plane LDS ring;
+//   4. barrier.
+// Each population is read from HBM by its owning tile; ring and z-halo
+// re-reads are shared with neighbouring workgroups, which the XCD-aware
+// block order keeps on the same L2.
+//
+// Waves: TY tile-row waves, 2 ring-row waves, 1 wave for the two ring
+// columns.  LDS plane layout: (TY + 2) rows x 66 columns, column 0 = x0 - 1.
+#pragma once
+
+#include "lb_collide.h"
+#include "lb_device.h"
+
+namespace lbk {
+
+struct FusedGrid {
+    int ntx, nty, nzc, zlen;
+};
+
+struct Box3 {
+    int x0, y0, z0, w, h, d;
+};
+
+// Cells whose pull touches a boundary (a z face or the head) are pulled with
+// the boundary rules by the preparation kernel; every other cell has only
+// fluid sources.
+__device__ __forceinline__ bool in_box(const DevParams &P, const Box3 &B, int x, int y, int z)
+{
+    if (B.w <= 0) return false;
+    int dx = x - B.x0, dy = y - B.y0;
+    dx = ((dx % P.nx) + P.nx) % P.nx;
+    dy = ((dy % P.ny) + P.ny) % P.ny;
+    return dx < B.w && dy < B.h && z >= B.z0 && z < B.z0 + B.d;
+}
+
+__device__ __forceinline__ bool prepared(const DevParams &P, const Box3 &head, int x, int y, int z)
+{
+    if (!P.periodic_z && (z == 0 || z == P.nz - 1)) return true;
+    return in_box(P, head, x, y, z);
+}
+
+__device__ __forceinline__ int wrap_any(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// The next step's pull reads the bare moments of this step near boundaries
+// only (wall density extrapolation, the pressure faces' velocity).
+__device__ __forceinline__ bool macro_needed(const DevParams &P, const HeadPos &H, int x, int y, int z)
+{
+    if (!P.periodic_z && (z <= 2 || z >= P.nz - 3)) return true;
+    if (!P.has_nozzle || (double)z < P.tip_z - 3.0) return false;
+    double dx = fabs((double)x - H.hx_c), dy = fabs((double)y - H.hy_c);
+    dx = fmin(dx, (double)P.nx - dx);
+    dy = fmin(dy, (double)P.ny - dy);
+    double lim = P.rout + 4.0;
+    return dx <= lim && dy <= lim;
+}
+
+template <typename R, int TY>
+__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos H, FusedGrid FG, Box3 head,
+                                                            const R *__restrict__ src, R *__restrict__ dst,
+                                                            const double *__restrict__ momd,
+                                                            const R *__restrict__ mom, const R *__restrict__ chi,
+                                                            const R *__restrict__ ghost, R *__restrict__ mac_next,
+                                                            int first)
+{
+    constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
+    __shared__ R chi_l[4][3][PL];
+    __shared__ double st_d[2][2][NI];
+    __shared__ R st_r[2][10][NI];
+
+    // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so
+    // block b handles tile (b % 8) * (nb / 8) + b / 8 and each XCD works on a
+    // contiguous band of tiles.
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int tx = t % FG.ntx, ty = (t / FG.ntx) % FG.nty, tz = t / (FG.ntx * FG.nty);
+    const int x0 = tx * 64, y0 = ty * TY, z0 = tz * FG.zlen;
+    const int z1 = min(z0 + FG.zlen, P.nz);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long N = P.N;
+
+    int cx, cy, row, col;
+    bool active = true;
+    if (wave < TY) {
+        cx = x0 + lane;
+        cy = y0 + wave;
+        row = wave + 1;
+        col = lane + 1;
+    } else if (wave == TY) {
+        cx = x0 + lane;
+        cy = y0 - 1;
+        row = 0;
+        col = lane + 1;
+    } else if (wave == TY + 1) {
+        cx = x0 + lane;
+        cy = y0 + TY;
+        row = TY + 1;
+        col = lane + 1;
+    } else {
+        if (lane < HH) {
+            cx = x0 - 1;
+            cy = y0 - 1 + lane;
+            row = lane;
+            col = 0;
+        } else if (lane < 2 * HH) {
+            cx = x0 + 64;
+            cy = y0 - 1 + lane - HH;
+            row = lane - HH;
+            col = 65;
+        } else {
+            cx = x0;
+            cy = y0;
+            row = 0;
+            col = 0;
+            active = false;
+        }
+    }
+    // tile cells outside the box are ring duty for the wrapped column
+    const bool tile = active && wave < TY && cx < P.nx && cy < P.ny;
+    const int xw = wrap_any(cx, P.nx), yw = wrap_any(cy, P.ny);
+    const int lidx = row * W + col;
+    const int ii = wave * 64 + lane;  // tile threads' state index
+    const bool shell_c = active && !far_from_head(P, H.hx_c, H.hy_c, xw, yw) &&
+                         column_class(P, H.hx_c, H.hy_c, xw, yw) == COL_SHELL;
+    // the column's part of the "prepared" test (fixed for the march)
+    const bool head_col = active && in_box(P, Box3{head.x0, head.y0, 0, head.w, head.h, P.nz}, xw, yw, 0);
+    const long long col_off = (long long)yw * P.nx + xw;
+    const long long plane_sz = (long long)P.nx * P.ny;
+    bool ok1 = false, ok2 = false;  // plane p-1 / p-2 of this tile cell is fluid
+
+    for (int p = z0 - 1; p <= z1 + 1; ++p) {
+        // ---- 1. issue the bulk loads of plane p
+        const bool load = active && p <= z1;
+        int zp = p;
+        bool ghost_plane = false;
+        if (zp < 0 || zp >= P.nz) {
+            if (P.periodic_z)
+                zp = wrap_any(zp, P.nz);
+            else
+                ghost_plane = true;
+        }
+        const bool own = tile && p >= z0 && p < z1;
+        const bool zface = !P.periodic_z && (zp == 0 || zp == P.nz - 1);
+        const bool prep = load && !ghost_plane && (zface || (head_col && zp >= head.z0 && zp < head.z0 + head.d));
+        const bool bulk = load && !ghost_plane && !prep;
+        const long long cell = ghost_plane ? 0 : col_off + (long long)zp * plane_sz;
+        R vT[lbq::Q], vY[lbq::Q];
+        if (bulk) pull_bulk_issue<R>(P, src, bulk_index(P, xw, yw, zp), (unsigned)cell, first != 0, vT, vY);
+        __builtin_amdgcn_sched_barrier(0);
+
+        // ---- 2. collide plane c = p - 2 (stencil planes p - 3 .. p - 1)
+        const int c = p - 2;
+        if (ok2) {
+            const int ss = c & 1;
+            const int sm = (c + 3) & 3, s0 = c & 3, sp1 = (c + 1) & 3;
+            Grad<R> G;
+#pragma unroll
+            for (int m = 0; m < 9; ++m) G.g[m] = R(0);
+#pragma unroll
+            for (int i = 1; i < lbq::Q; i += 2) {
+                const int X = lbq::cx(i), Yc = lbq::cy(i), Z = lbq::cz(i);
+                const int sa = Z > 0 ? sp1 : (Z < 0 ? sm : s0);
+                const int sb = Z > 0 ? sm : (Z < 0 ? sp1 : s0);
+                const int la = (row + Yc) * W + col + X, lb = (row - Yc) * W + col - X;
+                const R kk = R(3.0 * lbq::w(i));
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const R d = kk * (chi_l[sa][f][la] - chi_l[sb][f][lb]);
+                    if (X) G.g[3 * f + 0] += X > 0 ? d : -d;
+                    if (Yc) G.g[3 * f + 1] += Yc > 0 ? d : -d;
+                    if (Z) G.g[3 * f + 2] += Z > 0 ? d : -d;
+                }
+            }
+            CellState<R> C;
+            C.drho = st_d[ss][0][ii];
+            C.rY = st_d[ss][1][ii];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) C.j[a] = st_r[ss][a][ii];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) C.Pi[a] = st_r[ss][3 + a][ii];
+            C.om = st_r[ss][9][ii];
+            const long long ccell = col_off + (long long)c * plane_sz;
+            R rY, rB, u[3];
+            collide_state<R>(P, C, G, c, dst, dst + (long long)lbq::Q * N, ccell, N, rY, rB, u);
+            if (macro_needed(P, H, xw, yw, c)) {
+                mac_next[ccell] = rY;
+                mac_next[N + ccell] = rB;
+                mac_next[2 * N + ccell] = u[0];
+                mac_next[3 * N + ccell] = u[1];
+                mac_next[4 * N + ccell] = u[2];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        // ---- 3. reduce plane p: colour fields and the tile cell's state
+        bool cur_ok = false;
+        if (load) {
+            R cN, cY, cB;
+            if (ghost_plane) {
+                const long long plane = (long long)P.nx * P.ny;
+                const int face = zp < 0 ? 0 : 1;
+                const long long gc = (long long)yw * P.nx + xw;
+                cN = ghost[(face * 3 + 0) * plane + gc];
+                cY = ghost[(face * 3 + 1) * plane + gc];
+                cB = ghost[(face * 3 + 2) * plane + gc];
+            } else {
+                Mom<R> M;
+                mom_zero(M);
+                bool fluid = true;
+                if (prep) {
+                    // boundary cell (pulled with the boundary rules), head
+                    // solid (wall densities) or node just created
+                    cN = chi[cell];
+                    cY = chi[N + cell];
+                    cB = chi[2 * N + cell];
+                    fluid = !(shell_c && (double)zp >= P.tip_z);
+                    if (own && fluid) {
+                        M.dm[0] = momd[cell];
+                        M.dm[1] = momd[N + cell];
+#pragma unroll
+                        for (int m = 2; m < NMOM; ++m) M.m[m] = mom[(m - 2) * N + cell];
+                    }
+                } else {
+                    if (own)
+                        mom_add_all<R, true>(M, vT, vY);
+                    else
+                        mom_add_all<R, false>(M, vT, vY);
+                    chi_of<R>(P, R(M.dm[1]), R(P.rho_ref + M.dm[0] - M.dm[1]), cN, cY, cB);
+                }
+                if (own && fluid) {
+                    const CellState<R> C = cell_state<R>(P, M);
+                    const int ss = p & 1;
+                    st_d[ss][0][ii] = C.drho;
+                    st_d[ss][1][ii] = C.rY;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) st_r[ss][a][ii] = C.j[a];
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) st_r[ss][3 + a][ii] = C.Pi[a];
+                    st_r[ss][9][ii] = C.om;
+                    cur_ok = true;
+                }
+            }
+            const int cs = p & 3;
+            chi_l[cs][0][lidx] = cN;
+            chi_l[cs][1][lidx] = cY;
+            chi_l[cs][2][lidx] = cB;
+        }
+        ok2 = ok1;
+        ok1 = cur_ok;
+        __syncthreads();
+    }
+}
+
+}  // namespace lbk

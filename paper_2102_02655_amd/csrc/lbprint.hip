@@ -15,12 +15,15 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <algorithm>
 
 #include "../../include/lbprint.h"
 #include "lb_collide.h"
 #include "lb_device.h"
+#include "lb_fused.h"
 
 using namespace lbk;
 
@@ -28,6 +31,7 @@ namespace {
 
 constexpr int TPB = 256;       // threads per block of the per-cell kernels
 constexpr int NB_SPARSE = 64;  // fixed grid of the head-box kernels (deterministic slots)
+constexpr int NB_PRE = 512;    // fixed grid of the boundary preparation kernel
 constexpr int NSLOT = 6;       // per-block FP64 sums: wall Y, wall B, open Y, open B, deleted Y, deleted B
 constexpr int NPART = 6;       // per-block FP64 sums of the output: mass Y, B, momentum xyz, unstable
 
@@ -124,14 +128,50 @@ __global__ __launch_bounds__(TPB) void k_init(DevParams P, HeadPos H, const doub
     }
 }
 
-// Pull + moments.  commit = 1 adds this step's boundary fluxes and deleted
-// mass into the block's cumulative slot; commit = 0 writes them (pending
-// values for lb_moments) without touching the cumulative state.
+// Pull + moments of one cell at step t: moment set, colour fields, and into
+// acc the boundary fluxes of its pull (when fluxes) and, for a node the head
+// covers at t, its deleted mass.
+template <typename R>
+__device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
+                                             const R *__restrict__ mac, double *__restrict__ momd,
+                                             R *__restrict__ mom, R *__restrict__ chi, long long cell, int x, int y,
+                                             int z, bool first, bool fluxes, double (&acc)[NSLOT], int &any)
+{
+    bool near = !far_from_head(P, H.hx_p, H.hy_p, x, y) || !far_from_head(P, H.hx_c, H.hy_c, x, y);
+    bool sp = near && is_solid(P, H.hx_p, H.hy_p, x, y, z);
+    bool sc = near && is_solid(P, H.hx_c, H.hy_c, x, y, z);
+    if (sp) return;
+    Mom<R> M;
+    mom_zero(M);
+    Flux fl = {0.0, 0.0, 0.0, 0.0};
+    pull_all<R, true>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
+    if (!sc) {
+        momd[cell] = M.dm[0];
+        momd[P.N + cell] = M.dm[1];
+#pragma unroll
+        for (int q = 2; q < NMOM; ++q) mom[(q - 2) * P.N + cell] = M.m[q];
+        write_chi<R>(P, chi, cell, M.dm[1], P.rho_ref + M.dm[0] - M.dm[1]);
+    } else {
+        acc[4] += M.dm[1];
+        acc[5] += P.rho_ref + M.dm[0] - M.dm[1];
+        any = 1;
+    }
+    if (fluxes) {
+        acc[0] += fl.wallY;
+        acc[1] += fl.wallB;
+        acc[2] += fl.openY;
+        acc[3] += fl.openB;
+        any |= (fl.wallY != 0.0) | (fl.wallB != 0.0) | (fl.openY != 0.0) | (fl.openB != 0.0);
+    }
+}
+
+// Whole-box pull + moments (read-out path): writes this step's pending
+// boundary fluxes and deleted mass per block, touching no cumulative state.
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R *__restrict__ src,
                                                  const R *__restrict__ mac, double *__restrict__ momd,
                                                  R *__restrict__ mom, R *__restrict__ chi, double *__restrict__ slots,
-                                                 int first, int commit)
+                                                 int first)
 {
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
@@ -139,37 +179,39 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R
     if (cell < P.N) {
         int x, y, z;
         cell_xyz(P, cell, x, y, z);
-        bool near = !far_from_head(P, H.hx_p, H.hy_p, x, y) || !far_from_head(P, H.hx_c, H.hy_c, x, y);
-        bool sp = near && is_solid(P, H.hx_p, H.hy_p, x, y, z);
-        bool sc = near && is_solid(P, H.hx_c, H.hy_c, x, y, z);
-        if (!sp) {
-            Mom<R> M;
-            mom_zero(M);
-            Flux fl = {0.0, 0.0, 0.0, 0.0};
-            pull_all<R>(P, H, src, mac, x, y, z, cell, near, first != 0, M, fl);
-            if (!sc) {
-                momd[cell] = M.dm[0];
-                momd[P.N + cell] = M.dm[1];
-#pragma unroll
-                for (int q = 2; q < NMOM; ++q) mom[(q - 2) * P.N + cell] = M.m[q];
-                write_chi<R>(P, chi, cell, M.dm[1], P.rho_ref + M.dm[0] - M.dm[1]);
-            } else {
-                acc[4] = M.dm[1];
-                acc[5] = P.rho_ref + M.dm[0] - M.dm[1];
-            }
-            acc[0] = fl.wallY;
-            acc[1] = fl.wallB;
-            acc[2] = fl.openY;
-            acc[3] = fl.openB;
-            any = (fl.wallY != 0.0) | (fl.wallB != 0.0) | (fl.openY != 0.0) | (fl.openB != 0.0) | sc;
+        moments_cell<R>(P, H, src, mac, momd, mom, chi, cell, x, y, z, first != 0, true, acc, any);
+    }
+    block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, false);
+}
+
+// Boundary preparation of a time step: the cells whose pull touches a
+// boundary (the z faces' layers, the head's box) are pulled here with the
+// boundary rules of Sec. II.B; their moment sets and colour fields feed the
+// fused kernel, the wall densities and the created nodes.  The mass each
+// boundary rule adds and the mass of nodes the head covers are added to the
+// block's cumulative slot.  Boxes 1 and 2 skip cells of box 0 (the head box)
+// so that no cell is counted twice.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_pre(DevParams P, HeadPos H, Box3 b0, Box3 b1, Box3 b2, int nbox,
+                                             const R *__restrict__ src, const R *__restrict__ mac,
+                                             double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
+                                             double *__restrict__ slots, int first)
+{
+    double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
+    int any = 0;
+    for (int bi = 0; bi < nbox; ++bi) {
+        const Box3 B = bi == 0 ? b0 : (bi == 1 ? b1 : b2);
+        const long long total = (long long)B.w * B.h * B.d;
+        for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+            int ix = (int)(k % B.w), iy = (int)((k / B.w) % B.h), iz = (int)(k / ((long long)B.w * B.h));
+            int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
+            if (z < 0 || z >= P.nz) continue;
+            if (bi > 0 && in_box(P, b0, x, y, z)) continue;
+            moments_cell<R>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc, any);
         }
     }
-    if (commit) {
-        if (!__syncthreads_or(any)) return;
-        block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, true);
-    } else {
-        block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, false);
-    }
+    if (!__syncthreads_or(any)) return;
+    block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, true);
 }
 
 // Sec. II.B: nodes released by the head (solid at t-1, fluid at t) start at
@@ -318,89 +360,6 @@ __global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const dou
     ghost[(face * 3 + 2) * plane + c] = R(cB);
 }
 
-template <typename R>
-__device__ __forceinline__ void chi_at(const DevParams &P, const R *__restrict__ chi, const R *__restrict__ ghost,
-                                       int x, int y, int z, R &cN, R &cY, R &cB)
-{
-    if (z < 0 || z >= P.nz) {
-        if (P.periodic_z) {
-            z = wrap(z, P.nz);
-        } else {
-            long long plane = (long long)P.nx * P.ny;
-            int face = z < 0 ? 0 : 1;
-            long long c = (long long)y * P.nx + x;
-            cN = ghost[(face * 3 + 0) * plane + c];
-            cY = ghost[(face * 3 + 1) * plane + c];
-            cB = ghost[(face * 3 + 2) * plane + c];
-            return;
-        }
-    }
-    long long c = cidx(P, x, y, z);
-    cN = chi[c];
-    cY = chi[P.N + c];
-    cB = chi[2 * P.N + c];
-}
-
-// Colour gradients of Eq. (lattgrad), summed over opposite link pairs.
-template <typename R, int I = 1>
-__device__ __forceinline__ void grad_pairs(const DevParams &P, const R *__restrict__ chi, const R *__restrict__ ghost,
-                                           int x, int y, int z, Grad<R> &G)
-{
-    if constexpr (I < lbq::Q) {
-        constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-        R aN, aY, aB, bN, bY, bB;
-        chi_at<R>(P, chi, ghost, wrap(x + X, P.nx), wrap(y + Yc, P.ny), z + Z, aN, aY, aB);
-        chi_at<R>(P, chi, ghost, wrap(x - X, P.nx), wrap(y - Yc, P.ny), z - Z, bN, bY, bB);
-        const R k = R(3.0 * lbq::w(I));
-        const R dN = k * (aN - bN), dY = k * (aY - bY), dB = k * (aB - bB);
-        if (X) {
-            G.g[0] += X > 0 ? dN : -dN;
-            G.g[3] += X > 0 ? dY : -dY;
-            G.g[6] += X > 0 ? dB : -dB;
-        }
-        if (Yc) {
-            G.g[1] += Yc > 0 ? dN : -dN;
-            G.g[4] += Yc > 0 ? dY : -dY;
-            G.g[7] += Yc > 0 ? dB : -dB;
-        }
-        if (Z) {
-            G.g[2] += Z > 0 ? dN : -dN;
-            G.g[5] += Z > 0 ? dY : -dY;
-            G.g[8] += Z > 0 ? dB : -dB;
-        }
-        grad_pairs<R, I + 2>(P, chi, ghost, x, y, z, G);
-    }
-}
-
-template <typename R>
-__global__ __launch_bounds__(TPB) void k_collide(DevParams P, HeadPos H, const double *__restrict__ momd,
-                                                 const R *__restrict__ mom, const R *__restrict__ chi,
-                                                 const R *__restrict__ ghost, R *__restrict__ dst, R *__restrict__ mac)
-{
-    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
-    if (cell >= P.N) return;
-    int x, y, z;
-    cell_xyz(P, cell, x, y, z);
-    bool near = !far_from_head(P, H.hx_c, H.hy_c, x, y);
-    if (near && is_solid(P, H.hx_c, H.hy_c, x, y, z)) return;
-    Mom<R> M;
-    M.dm[0] = momd[cell];
-    M.dm[1] = momd[P.N + cell];
-#pragma unroll
-    for (int q = 2; q < NMOM; ++q) M.m[q] = mom[(q - 2) * P.N + cell];
-    Grad<R> G;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) G.g[q] = R(0);
-    grad_pairs<R>(P, chi, ghost, x, y, z, G);
-    R rY, rB, u[3];
-    collide_store<R>(P, M, G, z, dst, dst + (long long)lbq::Q * P.N, cell, P.N, rY, rB, u);
-    mac[cell] = rY;
-    mac[P.N + cell] = rB;
-    mac[2 * P.N + cell] = u[0];
-    mac[3 * P.N + cell] = u[1];
-    mac[4 * P.N + cell] = u[2];
-}
-
 // Fields for lb_moments: rho_Y, rho_B, physical velocity (j + F/2)/rho; block
 // sums of mass and momentum; instability flag.
 template <typename R, typename O>
@@ -446,36 +405,48 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const do
 
 // Deterministic final sums for lb_moments (one block):
 // out = mass[2], mom[3], wall[2], open[2], created[2], deleted[2], unstable.
-__global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part, const double *__restrict__ cum,
-                                                const double *__restrict__ pend, long long nbm,
+// Committed boundary fluxes live in the fused kernel's block slots, committed
+// deleted / created mass in the boundary kernels' slots; pend / pendc hold
+// the read-out's not-yet-committed values of the current step.
+__global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part, const double *__restrict__ pend,
+                                                long long nbm, const double *__restrict__ cumpre, int nbp,
                                                 const double *__restrict__ cumc, const double *__restrict__ pendc,
-                                                int nbc, double *__restrict__ out)
+                                                int nbs, double *__restrict__ out)
 {
     double v[14] = {0};
     for (long long b = threadIdx.x; b < nbm; b += TPB) {
         const double *p = part + b * NPART;
         for (int q = 0; q < 5; ++q) v[q] += p[q];
         v[13] = fmax(v[13], p[5]);
-        const double *c = cum + b * NSLOT, *d = pend + b * NSLOT;
-        v[5] += c[0] + d[0];
-        v[6] += c[1] + d[1];
-        v[7] += c[2] + d[2];
-        v[8] += c[3] + d[3];
-        v[11] += c[4] + d[4];
-        v[12] += c[5] + d[5];
+        const double *d = pend + b * NSLOT;
+        v[5] += d[0];
+        v[6] += d[1];
+        v[7] += d[2];
+        v[8] += d[3];
+        v[11] += d[4];
+        v[12] += d[5];
     }
-    for (int b = threadIdx.x; b < nbc; b += TPB) {
+    for (int b = threadIdx.x; b < nbp; b += TPB) {
+        const double *c = cumpre + (long long)b * NSLOT;
+        v[5] += c[0];
+        v[6] += c[1];
+        v[7] += c[2];
+        v[8] += c[3];
+        v[11] += c[4];
+        v[12] += c[5];
+    }
+    for (int b = threadIdx.x; b < nbs; b += TPB) {
         v[9] += cumc[2 * b] + pendc[2 * b];
         v[10] += cumc[2 * b + 1] + pendc[2 * b + 1];
     }
     __shared__ double red[14][TPB];
     for (int q = 0; q < 14; ++q) red[q][threadIdx.x] = v[q];
     __syncthreads();
-    for (int s = TPB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
+    for (int st = TPB / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
             for (int q = 0; q < 14; ++q)
-                red[q][threadIdx.x] =
-                    q == 13 ? fmax(red[q][threadIdx.x], red[q][threadIdx.x + s]) : red[q][threadIdx.x] + red[q][threadIdx.x + s];
+                red[q][threadIdx.x] = q == 13 ? fmax(red[q][threadIdx.x], red[q][threadIdx.x + st])
+                                              : red[q][threadIdx.x] + red[q][threadIdx.x + st];
         __syncthreads();
     }
     if (threadIdx.x == 0)
@@ -494,11 +465,38 @@ constexpr size_t ALIGN = 256;
 size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-    size_t pops, momd, mom, chi, ghost, mac, cum, pend, part, cumc, pendc, red, total;
-    long long nbm;
+    size_t pops, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, total;
+    long long nbm;   // blocks of the whole-box read-out kernels
+    FusedGrid fg;    // tiling of the fused step kernel
+    long long nbf;   // its block count
+    int ty;          // its tile height
 };
 
 size_t real_size(int storage) { return storage == LB_F64 ? 8 : 4; }
+
+// Fused kernel tile height per storage type (TY + 3 waves).  LDS: colour ring
+// 4 x 3 x 66 (TY + 2) values, state ring 2 x 64 TY x (2 FP64 + 10 values).
+constexpr int TY_F32 = 4;
+constexpr int TY_F64 = 5;
+
+FusedGrid fused_grid(const lb_params &p, int ty)
+{
+    FusedGrid g;
+    g.ntx = (p.nx + 63) / 64;
+    g.nty = (p.ny + ty - 1) / ty;
+    long long tiles = (long long)g.ntx * g.nty;
+    // enough blocks for two per CU on 256 CUs, z chunks of at least 8 planes
+    long long want = (1024 + tiles - 1) / tiles;
+    long long maxc = std::max(1, p.nz / 8);
+    g.nzc = (int)std::max(1LL, std::min(want, maxc));
+    if (const char *e = std::getenv("LBPRINT_ZLEN")) {
+        int z = std::atoi(e);
+        if (z > 0) g.nzc = (p.nz + z - 1) / z;
+    }
+    g.zlen = (p.nz + g.nzc - 1) / g.nzc;
+    g.nzc = (p.nz + g.zlen - 1) / g.zlen;
+    return g;
+}
 
 Layout layout_of(const lb_params &p)
 {
@@ -506,6 +504,9 @@ Layout layout_of(const lb_params &p)
     long long N = (long long)p.nx * p.ny * p.nz;
     size_t rs = real_size(p.storage);
     L.nbm = (N + TPB - 1) / TPB;
+    L.ty = p.storage == LB_F64 ? TY_F64 : TY_F32;
+    L.fg = fused_grid(p, L.ty);
+    L.nbf = (long long)L.fg.ntx * L.fg.nty * L.fg.nzc;
     size_t off = 0;
     L.pops = off;
     off += 2 * al(2 * lbq::Q * (size_t)N * rs);
@@ -518,13 +519,13 @@ Layout layout_of(const lb_params &p)
     L.ghost = off;
     off += al(2 * NCHI * (size_t)p.nx * p.ny * rs);
     L.mac = off;
-    off += al(NMAC * (size_t)N * rs);
-    L.cum = off;
-    off += al((size_t)L.nbm * NSLOT * 8);
+    off += 2 * al(NMAC * (size_t)N * rs);
     L.pend = off;
     off += al((size_t)L.nbm * NSLOT * 8);
     L.part = off;
     off += al((size_t)L.nbm * NPART * 8);
+    L.cumpre = off;
+    off += al((size_t)NB_PRE * NSLOT * 8);
     L.cumc = off;
     off += al(NB_SPARSE * 2 * 8);
     L.pendc = off;
@@ -744,23 +745,36 @@ Box head_box(const lb_handle *h, double xlo, double xhi, double ylo, double yhi)
 }
 
 template <typename R>
-lb_status run_moments(lb_handle *h, int commit)
+R *pops_at(lb_handle *h, int which)
+{
+    return as<R>(h, h->L.pops + which * al(2 * lbq::Q * (size_t)h->P.N * sizeof(R)));
+}
+
+// macro buffer written at step t is t & 1; the pull of step t reads (t - 1) & 1
+template <typename R>
+R *mac_at(lb_handle *h, long t)
+{
+    return as<R>(h, h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.N * sizeof(R)));
+}
+
+// Read-out pull: moments of the whole box at the current step, pending
+// fluxes / deletions / creations (nothing committed).
+template <typename R>
+lb_status run_readout(lb_handle *h)
 {
     double xl, xh, yl, yh;
     HeadPos H = heads(h, &xl, &xh, &yl, &yh);
     const Layout &L = h->L;
-    R *src = as<R>(h, L.pops + h->cur * al(2 * lbq::Q * (size_t)h->P.N * sizeof(R)));
-    double *slots = as<double>(h, commit ? L.cum : L.pend);
-    hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, src, as<R>(h, L.mac),
-                       as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), slots, h->first, commit);
+    hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, pops_at<R>(h, h->cur),
+                       mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                       as<double>(h, L.pend), h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
         Box b = head_box(h, xl, xh, yl, yh);
         hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h,
-                           b.d, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
-                           as<double>(h, commit ? L.cumc : L.pendc), commit);
+                           b.d, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.pendc), 0);
         if (lb_status s = check_launch(h, "k_create")) return s;
-    } else if (!commit) {
+    } else {
         if (hipMemsetAsync(as<double>(h, L.pendc), 0, NB_SPARSE * 2 * 8, h->stream) != hipSuccess)
             return fail(h, LB_EDEVICE, "hipMemsetAsync");
     }
@@ -768,18 +782,54 @@ lb_status run_moments(lb_handle *h, int commit)
 }
 
 template <typename R>
+lb_status launch_fused(lb_handle *h, const HeadPos &H, const Box3 &head)
+{
+    constexpr int TY = sizeof(R) == 8 ? TY_F64 : TY_F32;
+    const Layout &L = h->L;
+    hipLaunchKernelGGL((k_fused<R, TY>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P, H, L.fg,
+                       head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
+                       as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t), h->first);
+    return check_launch(h, "k_fused");
+}
+
+// One time step: boundary preparation (pulls of the cells next to the z faces
+// and the head, node creation, wall densities, ghost layers), then the fused
+// step kernel over the whole box.
+template <typename R>
 lb_status run_step(lb_handle *h)
 {
-    if (lb_status s = run_moments<R>(h, 1)) return s;
     double xl, xh, yl, yh;
     HeadPos H = heads(h, &xl, &xh, &yl, &yh);
     const Layout &L = h->L;
+    Box3 bx[3] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
+    Box hb = {0, 0, 0, 0, 0, 0};
     if (h->p.has_nozzle) {
-        Box b = head_box(h, xl, xh, yl, yh);
-        long long tot = (long long)b.w * b.h * b.d;
+        hb = head_box(h, xl, xh, yl, yh);
+        int z0 = std::max(0, hb.z0 - 1);
+        bx[0] = Box3{hb.x0, hb.y0, z0, hb.w, hb.h, h->p.nz - z0};
+    }
+    int nbox = 1;
+    if (!h->P.periodic_z) {
+        bx[nbox++] = Box3{0, 0, 0, h->p.nx, h->p.ny, 1};
+        if (h->p.nz > 1) bx[nbox++] = Box3{0, 0, h->p.nz - 1, h->p.nx, h->p.ny, 1};
+    }
+    if (h->p.has_nozzle || !h->P.periodic_z) {
+        hipLaunchKernelGGL(k_pre<R>, dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, H, bx[0], bx[1], bx[2], nbox,
+                           pops_at<R>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
+                           as<R>(h, L.chi), as<double>(h, L.cumpre), h->first);
+        if (lb_status s = check_launch(h, "k_pre")) return s;
+    }
+    if (h->p.has_nozzle) {
+        if (!h->first) {
+            hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, H, hb.x0, hb.y0, hb.z0,
+                               hb.w, hb.h, hb.d, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                               as<double>(h, L.cumc), 1);
+            if (lb_status s = check_launch(h, "k_create")) return s;
+        }
+        long long tot = (long long)hb.w * hb.h * hb.d;
         unsigned nb = (unsigned)std::min<long long>((tot + TPB - 1) / TPB, 4096);
-        hipLaunchKernelGGL(k_wall<R>, dim3(nb), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h, b.d,
-                           as<double>(h, L.momd), as<R>(h, L.chi));
+        hipLaunchKernelGGL(k_wall<R>, dim3(nb), dim3(TPB), 0, h->stream, h->P, H, hb.x0, hb.y0, hb.z0, hb.w, hb.h,
+                           hb.d, as<double>(h, L.momd), as<R>(h, L.chi));
         if (lb_status s = check_launch(h, "k_wall")) return s;
     }
     if (!h->P.periodic_z) {
@@ -788,12 +838,7 @@ lb_status run_step(lb_handle *h)
                            as<double>(h, L.momd), as<R>(h, L.ghost));
         if (lb_status s = check_launch(h, "k_ghost")) return s;
     }
-    size_t psz = al(2 * lbq::Q * (size_t)h->P.N * sizeof(R));
-    R *dst = as<R>(h, L.pops + (1 - h->cur) * psz);
-    hipLaunchKernelGGL(k_collide<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H,
-                       as<double>(h, L.momd), as<R>(h, L.mom),
-                       as<R>(h, L.chi), as<R>(h, L.ghost), dst, as<R>(h, L.mac));
-    if (lb_status s = check_launch(h, "k_collide")) return s;
+    if (lb_status s = launch_fused<R>(h, H, bx[0])) return s;
     h->cur = 1 - h->cur;
     h->t += 1;
     h->first = 0;
@@ -814,7 +859,7 @@ lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, i
 {
     const Layout &L = h->L;
     const long long N = h->P.N;
-    if (lb_status s = run_moments<R>(h, 0)) return s;
+    if (lb_status s = run_readout<R>(h)) return s;
     // outputs: direct to device pointers, or staged in the spare population buffer
     size_t psz = al(2 * lbq::Q * (size_t)N * sizeof(R));
     char *stage = h->ws + L.pops + (1 - h->cur) * psz;
@@ -828,9 +873,9 @@ lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, i
     lb_status s = dtype == 0 ? run_output<R, double>(h, (double *)dry, (double *)drb, (double *)du)
                              : run_output<R, float>(h, (float *)dry, (float *)drb, (float *)du);
     if (s) return s;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, h->stream, as<double>(h, L.part), as<double>(h, L.cum),
-                       as<double>(h, L.pend), L.nbm, as<double>(h, L.cumc), as<double>(h, L.pendc), NB_SPARSE,
-                       as<double>(h, L.red));
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, h->stream, as<double>(h, L.part), as<double>(h, L.pend),
+                       L.nbm, as<double>(h, L.cumpre), NB_PRE, as<double>(h, L.cumc), as<double>(h, L.pendc),
+                       NB_SPARSE, as<double>(h, L.red));
     if ((s = check_launch(h, "k_reduce"))) return s;
     double red[16];
     hipError_t e = hipMemcpyAsync(red, as<double>(h, L.red), 14 * 8, hipMemcpyDeviceToHost, h->stream);
@@ -903,8 +948,7 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     hipError_t e = hipMemcpyAsync(dry, rho_y, N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(drb, rho_b, N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * 8, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cum, 0, L.pend - L.cum, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cumc, 0, L.pendc - L.cumc, h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cumpre, 0, L.pendc - L.cumpre, h->stream);
     if (e != hipSuccess) {
         std::string m = std::string("lb_create: ") + hipGetErrorString(e);
         delete h;
