@@ -5,14 +5,19 @@ head moving at 0.01 along x, power-law ink n = 0.5, FP32 storage and
 arithmetic, synthetic initial state (ink-filled nozzle in air).  One step is
 one full time step of the method on every cell.
 
-Prints one JSON line (MLUPS, HBM roofline fraction of the dominant kernel,
-and the FP64 CPU oracle timed on a bounded sample of the same workload).
+Prints one JSON line: whole-step MLUPS, the HBM roofline of the dominant
+kernel (the fused step kernel, timed with HIP events on the library's stream
+over the timed region) and the FP64 CPU oracle timed on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -20,14 +25,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per lattice update: each of the 2 x 19 populations read
+# once and written once.
 BYTES_PER_LU = {"f64": 608, "f32": 304}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_print_bed_512x256x128_f32_traffic.md")
+
+
+def source_digest() -> str:
+    """SHA-256 over the HIP sources and the C header (sorted by name)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2102_02655_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "lbprint.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per launch of the fused kernel from the committed PMC
+    summary, or None when the kernel sources changed since it was taken."""
+    if storage != "f32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not (m_sha and m_b) or m_sha.group(1) != source_digest():
+        return None
+    return float(m_b.group(1))
 
 
 def cpu_baseline(seconds: float = 15.0):
     """The FP64 oracle on the 128x64x32 crop of the same set-up, as many steps
     as fit in about `seconds`, on all host threads."""
-    import numpy as np  # noqa: F401
-
     from oracle import oracle as O
     from paper_2102_02655_amd import workloads as W
 
@@ -47,6 +78,21 @@ def cpu_baseline(seconds: float = 15.0):
             "sample": f"128x64x32 crop of the print-bed set-up, {steps} steps after 1 warm-up, FP64"}
 
 
+def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
+    """A plain elementwise copy of known size (read nbytes, write nbytes),
+    used to scale the PMC byte counters."""
+    import torch
+
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(f"copy probe: {reps} x torch.neg over {nbytes} B (read {nbytes} B + write {nbytes} B per launch)",
+          file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,15 +100,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", action="store_true", help="first run a plain copy of known size (PMC scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
 
     from paper_2102_02655_amd import lbprint, workloads as W
 
+    if args.copy_probe:
+        copy_probe()
     cfg = W.print_bed(n=0.5, storage=args.storage)
     ry, rb = W.nozzle_fields(cfg)
     nx, ny, nz = cfg["shape"]
@@ -70,14 +119,20 @@ def main():
     sim = lbprint.Sim(cfg, ry, rb, device="cuda:0")
     sim.step(args.warmup)
     torch.cuda.synchronize()
+    sim.timing(True)
     t0 = time.perf_counter()
     sim.step(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    sim.timing(False)
+    tm = sim.timing_read()
     _, _, _, cons = sim.moments(dtype="float32")
     mlups = cells * args.steps / dt / 1e6
     bpl = BYTES_PER_LU[args.storage]
-    achieved = bpl * mlups * 1e6 / 1e9
+    k_ms = tm["step_ms"] / max(tm["steps"], 1)
+    alg_bytes = bpl * cells
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage)
     out = {
         "metric": "MLUPS",
         "value": mlups,
@@ -91,11 +146,13 @@ def main():
         "vs_baseline": None,
         "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": f"print-bed filament D3Q19 {nx}x{ny}x{nz}, moving head, power-law n=0.5",
+        "config": {"workload": f"print-bed filament, D3Q19 {nx}x{ny}x{nz}, moving head u=0.01, power-law n=0.5",
                    "cells": cells, "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "scope": "whole step, algorithmic bytes"},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fused", "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
+                     "prep_ms": tm["prep_ms"] / max(tm["steps"], 1),
+                     "whole_step_GBs": bpl * mlups * 1e6 / 1e9},
         "mass": list(map(float, cons["mass"])),
     }
     if not args.no_cpu:

@@ -34,7 +34,8 @@
  *     handle until lb_destroy().  The library never allocates or frees device
  *     memory on this path.
  *   - The caller owns the HIP stream; every kernel and copy of a handle is
- *     enqueued on it.  Only lb_moments() synchronises it.
+ *     enqueued on it.  lb_create(), lb_moments(), lb_timing_read() and
+ *     lb_step() with check_interval > 0 synchronise it.
  */
 #ifndef LBPRINT_H
 #define LBPRINT_H
@@ -142,6 +143,18 @@ lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is
 
 /* Current step count. */
 long lb_time(const lb_handle *h);
+
+/* Measurement aid: kernel timing with HIP events on the handle's stream.
+ * lb_timing(h, 1) starts recording, at every following step, an event before
+ * the step's first kernel, one before the fused step kernel and one after it;
+ * lb_timing(h, 0) stops recording (what was recorded stays readable).
+ * lb_timing_read() waits for the recorded events, returns the summed duration
+ * of the fused step kernel (step_ms), of the boundary preparation kernels
+ * that precede it (prep_ms) and the number of timed steps, then clears the
+ * record.  Any output pointer may be NULL.  LB_EDEVICE if a HIP event call
+ * fails (the events are host-side runtime objects; no device memory). */
+lb_status lb_timing(lb_handle *h, int enable);
+lb_status lb_timing_read(lb_handle *h, double *step_ms, double *prep_ms, long *steps);
 
 /* Release the handle (host memory only; the workspace stays the caller's). */
 lb_status lb_destroy(lb_handle *h);

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 #include <algorithm>
 
 #include "../../include/lbprint.h"
@@ -672,6 +673,16 @@ struct lb_handle {
     int first;
     int unstable;
     std::string err;
+    // kernel timing (lb_timing): three events per timed step
+    int timing = 0;
+    std::vector<hipEvent_t> ev;
+    size_t nev = 0;
+    double acc_step = 0.0, acc_prep = 0.0;
+    long acc_n = 0;
+    ~lb_handle()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -781,6 +792,45 @@ lb_status run_readout(lb_handle *h)
     return LB_OK;
 }
 
+// Fold the recorded events into the running sums (waits for them).
+lb_status timing_fold(lb_handle *h)
+{
+    for (size_t k = 0; k + 2 < h->nev; k += 3) {
+        float a = 0.f, b = 0.f;
+        hipError_t e = hipEventSynchronize(h->ev[k + 2]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&a, h->ev[k], h->ev[k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, h->ev[k + 1], h->ev[k + 2]);
+        if (e != hipSuccess) {
+            h->nev = 0;
+            return fail(h, LB_EDEVICE, std::string("timing events: ") + hipGetErrorString(e));
+        }
+        h->acc_prep += a;
+        h->acc_step += b;
+        h->acc_n += 1;
+    }
+    h->nev = 0;
+    return LB_OK;
+}
+
+constexpr size_t MAX_TIMED_EVENTS = 3 * 1024;
+
+// Record timing event k (0: step start, 1: before the fused kernel, 2: after).
+lb_status timing_mark(lb_handle *h, int k)
+{
+    if (!h->timing) return LB_OK;
+    if (k == 0) h->nev -= h->nev % 3;  // drop the marks of a step that failed part-way
+    if (k == 0 && h->nev + 3 > MAX_TIMED_EVENTS)
+        if (lb_status s = timing_fold(h)) return s;
+    if (h->nev >= h->ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return fail(h, LB_EDEVICE, "hipEventCreate");
+        h->ev.push_back(e);
+    }
+    if (hipEventRecord(h->ev[h->nev], h->stream) != hipSuccess) return fail(h, LB_EDEVICE, "hipEventRecord");
+    h->nev += 1;
+    return LB_OK;
+}
+
 template <typename R>
 lb_status launch_fused(lb_handle *h, const HeadPos &H, const Box3 &head)
 {
@@ -803,6 +853,7 @@ lb_status run_step(lb_handle *h)
     const Layout &L = h->L;
     Box3 bx[3] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
     Box hb = {0, 0, 0, 0, 0, 0};
+    if (lb_status s = timing_mark(h, 0)) return s;
     if (h->p.has_nozzle) {
         hb = head_box(h, xl, xh, yl, yh);
         int z0 = std::max(0, hb.z0 - 1);
@@ -838,7 +889,9 @@ lb_status run_step(lb_handle *h)
                            as<double>(h, L.momd), as<R>(h, L.ghost));
         if (lb_status s = check_launch(h, "k_ghost")) return s;
     }
+    if (lb_status s = timing_mark(h, 1)) return s;
     if (lb_status s = launch_fused<R>(h, H, bx[0])) return s;
+    if (lb_status s = timing_mark(h, 2)) return s;
     h->cur = 1 - h->cur;
     h->t += 1;
     h->first = 0;
@@ -998,6 +1051,25 @@ lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is
 }
 
 long lb_time(const lb_handle *h) { return h ? h->t : -1; }
+
+lb_status lb_timing(lb_handle *h, int enable)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    h->timing = enable != 0;
+    return LB_OK;
+}
+
+lb_status lb_timing_read(lb_handle *h, double *step_ms, double *prep_ms, long *steps)
+{
+    if (!h) return fail(nullptr, LB_EINVAL, "null handle");
+    if (lb_status s = timing_fold(h)) return s;
+    if (step_ms) *step_ms = h->acc_step;
+    if (prep_ms) *prep_ms = h->acc_prep;
+    if (steps) *steps = h->acc_n;
+    h->acc_step = h->acc_prep = 0.0;
+    h->acc_n = 0;
+    return LB_OK;
+}
 
 lb_status lb_destroy(lb_handle *h)
 {

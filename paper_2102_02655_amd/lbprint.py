@@ -19,8 +19,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16dev": 2, "f16dev": 3}
 RHEOLOGY = {"newtonian": 0, "power_law": 1, "cross": 2}
 FACE = {"periodic": 0, "wall": 1, "pressure": 2}
 
-EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_moments", "lb_time", "lb_destroy", "lb_strerror",
-           "lb_last_error")
+EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_moments", "lb_time", "lb_timing", "lb_timing_read",
+           "lb_destroy", "lb_strerror", "lb_last_error")
 
 _d2 = C.c_double * 2
 _d3 = C.c_double * 3
@@ -96,12 +96,14 @@ def lib():
         L.lb_moments.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Conserved)]
         L.lb_time.argtypes = [vp]
         L.lb_time.restype = C.c_long
+        L.lb_timing.argtypes = [vp, C.c_int]
+        L.lb_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_long)]
         L.lb_destroy.argtypes = [vp]
         L.lb_strerror.argtypes = [C.c_int]
         L.lb_strerror.restype = C.c_char_p
         L.lb_last_error.argtypes = [vp]
         L.lb_last_error.restype = C.c_char_p
-        for f in ("lb_footprint", "lb_create", "lb_step", "lb_moments", "lb_destroy"):
+        for f in ("lb_footprint", "lb_create", "lb_step", "lb_moments", "lb_timing", "lb_timing_read", "lb_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -237,6 +239,21 @@ class Sim:
         if rc != LB_OK:
             _raise(rc, self._h)
         return cons.as_dict()
+
+    def timing(self, enable: bool = True) -> None:
+        """Start (or stop) HIP-event timing of the step kernels."""
+        rc = lib().lb_timing(self._h, 1 if enable else 0)
+        if rc != LB_OK:
+            _raise(rc, self._h)
+
+    def timing_read(self) -> dict:
+        """Summed durations (ms) of the fused step kernel and of the boundary
+        preparation kernels over the timed steps; clears the record."""
+        a, b, n = C.c_double(), C.c_double(), C.c_long()
+        rc = lib().lb_timing_read(self._h, C.byref(a), C.byref(b), C.byref(n))
+        if rc != LB_OK:
+            _raise(rc, self._h)
+        return {"step_ms": a.value, "prep_ms": b.value, "steps": int(n.value)}
 
     def close(self) -> None:
         if getattr(self, "_h", None):
