@@ -15,6 +15,8 @@
 //           + beta rho_Y rho_B / rho^2 cos(phi_i) sum_k rho_k phi_i^k.
 #pragma once
 
+#include <utility>
+
 #include "lb_device.h"
 
 namespace lbk {
@@ -49,16 +51,18 @@ struct OutCoef {
     double fracY;
 };
 
+// Store of link I into the population planes pT (set T) and pY (set Y) at
+// byte offset cellb.  The next step reads these once, a full sweep later, so
+// the stores are non-temporal.
 template <typename R, int I>
-__device__ __forceinline__ void store_one(const DevParams &P, const OutCoef<R> &K, R *__restrict__ dT,
-                                          R *__restrict__ dY, unsigned cell, long long N)
+__device__ __forceinline__ void store_one(const DevParams &P, const OutCoef<R> &K, gchar *pT, gchar *pY,
+                                          unsigned cellb)
 {
+    typedef __attribute__((address_space(1))) R gR;
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    R Tst;
-    double Yst;
+    R Tst, cgw = R(0);
     if constexpr (I == 0) {
         Tst = K.t0;
-        Yst = K.fracY * (lbq::w(0) * P.rho_ref + (double)Tst);
     } else {
         R q = K.k1;
         if (X) q += X > 0 ? K.ax : -K.ax;
@@ -76,22 +80,29 @@ __device__ __forceinline__ void store_one(const DevParams &P, const OutCoef<R> &
         if (X) cg += X > 0 ? K.rx : -K.rx;
         if (Yc) cg += Yc > 0 ? K.ry : -K.ry;
         if (Z) cg += Z > 0 ? K.rz : -K.rz;
-        // the ink's share, formed in FP64 so that sum_i f^Y_i = rho_Y holds to
-        // the final rounding of each stored value
-        Yst = K.fracY * (lbq::w(I) * P.rho_ref + (double)Tst) + (double)(wi * R(lbq::inv_len(I)) * cg);
+        cgw = wi * R(lbq::inv_len(I)) * cg;
     }
-    (dT + (long long)I * N)[cell] = Tst;
-    (dY + (long long)I * N)[cell] = R(Yst);
+    // the ink's share fracY (w_i rho_ref + T_i) + recolouring, formed in FP64
+    // so that sum_i f^Y_i = rho_Y holds to the final rounding of each stored
+    // value (an FP32 fracY, or any FP32 rounding of fracY T_i, would bias
+    // every cell of a uniform region alike)
+    const R Yst = R(__builtin_fma(K.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
+    __builtin_nontemporal_store(Tst, reinterpret_cast<gR *>(pT + cellb));
+    __builtin_nontemporal_store(Yst, reinterpret_cast<gR *>(pY + cellb));
 }
 
-template <typename R, int I = 0>
-__device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &K, R *__restrict__ dT,
-                                          R *__restrict__ dY, unsigned cell, long long N)
+// The 38 stores; base: population plane 0 of the destination set, pstride:
+// bytes per population plane.
+template <typename R>
+__device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &K, gchar *base,
+                                          unsigned long long pstride, unsigned cellb)
 {
-    if constexpr (I < lbq::Q) {
-        store_one<R, I>(P, K, dT, dY, cell, N);
-        store_all<R, I + 1>(P, K, dT, dY, cell, N);
-    }
+    gchar *pT = base;
+    gchar *pY = base + (unsigned long long)lbq::Q * pstride;
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        ((store_one<R, I>(P, K, pT + (unsigned long long)I * pstride, pY + (unsigned long long)I * pstride, cellb)),
+         ...);
+    }(std::make_integer_sequence<int, lbq::Q>{});
 }
 
 // What the collision needs of a cell, derived from its moment set: the two
@@ -152,7 +163,7 @@ __device__ __forceinline__ CellState<R> cell_state(const DevParams &P, const Mom
 // rho_Y, rho_B and the bare velocity for the boundary rules of the next pull.
 template <typename R>
 __device__ __forceinline__ void collide_state(const DevParams &P, const CellState<R> &C, const Grad<R> &G, int z,
-                                              R *__restrict__ dT, R *__restrict__ dY, long long cell, long long N,
+                                              char *__restrict__ dst, unsigned long long pstride, unsigned cellb,
                                               R &out_rY, R &out_rB, R (&out_u)[3])
 {
     const double rho_d = P.rho_ref + C.drho;
@@ -220,7 +231,7 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
     K.ry = rec * G.g[1];
     K.rz = rec * G.g[2];
     K.fracY = fracY_d;
-    store_all<R>(P, K, dT, dY, (unsigned)cell, N);
+    store_all<R>(P, K, fresh_global(dst), fresh_uniform(pstride), cellb);
     out_rY = rY;
     out_rB = rB;
     out_u[0] = ux;

@@ -326,22 +326,51 @@ __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, c
     }
 }
 
+// A uniform (scalar) value the optimiser must treat as new at this point:
+// derived addresses are then formed where they are used instead of being
+// hoisted out of a loop and kept (and spilled) for its whole length.
+template <typename T>
+__device__ __forceinline__ T fresh_uniform(T v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Global-memory pointers (address space 1): loads and stores through them are
+// global (not flat) instructions with a scalar base.
+typedef __attribute__((address_space(1))) char gchar;
+typedef __attribute__((address_space(1))) const char gcchar;
+
+template <typename P>
+__device__ __forceinline__ gchar *fresh_global(P *p)
+{
+    return (gchar *)fresh_uniform((unsigned long long)p);
+}
+
+template <typename P>
+__device__ __forceinline__ gcchar *fresh_global_c(const P *p)
+{
+    return (gcchar *)fresh_uniform((unsigned long long)p);
+}
+
 // Pull of a cell none of whose links touches a boundary (all 18 sources are
 // fluid at t-1): plain shifted loads, x and y periodic, z periodic or inside.
-// Source offsets are 32-bit (the population plane base is a scalar), so each
-// load needs one address register.
+// Addresses are a scalar plane base plus a 32-bit byte offset (one address
+// register per load, no 64-bit vector arithmetic); a population plane is
+// below 4 GiB (checked at creation).
 struct BulkIdx {
-    unsigned xo[3], yo[3], zo[3];  // offsets of x-1..x+1, rows y-1..y+1, planes z-1..z+1
+    unsigned xo[3], yo[3], zo[3];  // byte offsets of x-1..x+1, rows y-1..y+1, planes z-1..z+1
 };
 
+template <typename R>
 __device__ __forceinline__ BulkIdx bulk_index(const DevParams &P, int x, int y, int z)
 {
     BulkIdx b;
-    const unsigned nx = (unsigned)P.nx, plane = (unsigned)P.nx * (unsigned)P.ny;
+    const unsigned s = sizeof(R), row = (unsigned)P.nx * s, plane = (unsigned)P.nx * (unsigned)P.ny * s;
 #pragma unroll
     for (int d = -1; d <= 1; ++d) {
-        b.xo[d + 1] = (unsigned)wrap(x + d, P.nx);
-        b.yo[d + 1] = (unsigned)wrap(y + d, P.ny) * nx;
+        b.xo[d + 1] = (unsigned)wrap(x + d, P.nx) * s;
+        b.yo[d + 1] = (unsigned)wrap(y + d, P.ny) * row;
         b.zo[d + 1] = (unsigned)wrap(z + d, P.nz) * plane;
     }
     return b;
@@ -358,32 +387,25 @@ __device__ __forceinline__ void mom_add_all(Mom<R> &M, const R (&vT)[lbq::Q], co
 }
 
 // The 38 loads of a bulk pull (issued together, used later: the march keeps
-// them in flight across another plane's collision).
-template <typename R>
-__device__ __forceinline__ void pull_bulk_issue(const DevParams &P, const R *__restrict__ src, const BulkIdx &B,
-                                                unsigned cell, bool first, R (&vT)[lbq::Q], R (&vY)[lbq::Q])
+// them in flight across another plane's collision).  base: population plane
+// 0 of the source set; pstride: bytes per population plane; cellb: the
+// cell's own byte offset (the first step reads the cell's own slots: the
+// initial state is an equilibrium).
+template <typename R, bool FIRST>
+__device__ __forceinline__ void pull_bulk_issue(gcchar *base, unsigned long long pstride, const BulkIdx &B,
+                                                unsigned cellb, R (&vT)[lbq::Q], R (&vY)[lbq::Q])
 {
-    const long long N = P.N;
+    typedef __attribute__((address_space(1))) const R gR;
+    gcchar *pT = base;
+    gcchar *pY = base + (unsigned long long)lbq::Q * pstride;
 #pragma unroll
     for (int I = 0; I < lbq::Q; ++I) {
-        // 32-bit cell offset into the population's plane (a scalar base)
-        const unsigned sc = first ? cell : B.zo[1 - lbq::cz(I)] + B.yo[1 - lbq::cy(I)] + B.xo[1 - lbq::cx(I)];
-        vT[I] = (src + (long long)I * N)[sc];
-        vY[I] = (src + (long long)(lbq::Q + I) * N)[sc];
+        const unsigned off = FIRST ? cellb : B.zo[1 - lbq::cz(I)] + B.yo[1 - lbq::cy(I)] + B.xo[1 - lbq::cx(I)];
+        vT[I] = *reinterpret_cast<gR *>(pT + off);
+        vY[I] = *reinterpret_cast<gR *>(pY + off);
+        pT += pstride;
+        pY += pstride;
     }
-}
-
-// All 38 loads are issued before any is used (a scheduling barrier keeps the
-// compiler from interleaving them with the sums), so a cell costs one memory
-// round trip.
-template <typename R, bool FULL>
-__device__ __forceinline__ void pull_bulk(const DevParams &P, const R *__restrict__ src, const BulkIdx &B,
-                                          unsigned cell, bool first, Mom<R> &M)
-{
-    R vT[lbq::Q], vY[lbq::Q];
-    pull_bulk_issue<R>(P, src, B, cell, first, vT, vY);
-    __builtin_amdgcn_sched_barrier(0);
-    mom_add_all<R, FULL>(M, vT, vY);
 }
 
 // Colour fields of a site from its densities: rho^N (the standard phase field

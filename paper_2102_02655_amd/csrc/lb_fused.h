@@ -74,13 +74,12 @@ __device__ __forceinline__ bool macro_needed(const DevParams &P, const HeadPos &
     return dx <= lim && dy <= lim;
 }
 
-template <typename R, int TY>
+template <typename R, int TY, bool FIRST>
 __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos H, FusedGrid FG, Box3 head,
                                                             const R *__restrict__ src, R *__restrict__ dst,
                                                             const double *__restrict__ momd,
                                                             const R *__restrict__ mom, const R *__restrict__ chi,
-                                                            const R *__restrict__ ghost, R *__restrict__ mac_next,
-                                                            int first)
+                                                            const R *__restrict__ ghost, R *__restrict__ mac_next)
 {
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     __shared__ R chi_l[4][3][PL];
@@ -146,6 +145,7 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos
     const bool head_col = active && in_box(P, Box3{head.x0, head.y0, 0, head.w, head.h, P.nz}, xw, yw, 0);
     const long long col_off = (long long)yw * P.nx + xw;
     const long long plane_sz = (long long)P.nx * P.ny;
+    const unsigned long long pstride = (unsigned long long)N * sizeof(R);  // bytes per population plane
     bool ok1 = false, ok2 = false;  // plane p-1 / p-2 of this tile cell is fluid
 
     for (int p = z0 - 1; p <= z1 + 1; ++p) {
@@ -165,7 +165,9 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos
         const bool bulk = load && !ghost_plane && !prep;
         const long long cell = ghost_plane ? 0 : col_off + (long long)zp * plane_sz;
         R vT[lbq::Q], vY[lbq::Q];
-        if (bulk) pull_bulk_issue<R>(P, src, bulk_index(P, xw, yw, zp), (unsigned)cell, first != 0, vT, vY);
+        if (bulk)
+            pull_bulk_issue<R, FIRST>(fresh_global_c(src), fresh_uniform(pstride),
+                                      bulk_index<R>(P, xw, yw, zp), (unsigned)(cell * (long long)sizeof(R)), vT, vY);
         __builtin_amdgcn_sched_barrier(0);
 
         // ---- 2. collide plane c = p - 2 (stencil planes p - 3 .. p - 1)
@@ -201,7 +203,8 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos
             C.om = st_r[ss][9][ii];
             const long long ccell = col_off + (long long)c * plane_sz;
             R rY, rB, u[3];
-            collide_state<R>(P, C, G, c, dst, dst + (long long)lbq::Q * N, ccell, N, rY, rB, u);
+            collide_state<R>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,
+                             (unsigned)(ccell * (long long)sizeof(R)), rY, rB, u);
             if (macro_needed(P, H, xw, yw, c)) {
                 mac_next[ccell] = rY;
                 mac_next[N + ccell] = rB;

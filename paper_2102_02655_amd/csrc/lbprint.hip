@@ -541,6 +541,8 @@ const char *validate(const lb_params &p)
 {
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "box dimensions must be positive";
     if ((long long)p.nx * p.ny * p.nz > (1LL << 34)) return "box too large";
+    if ((long long)p.nx * p.ny * p.nz * (long long)real_size(p.storage) >= (1LL << 32))
+        return "box too large: one population plane must stay below 4 GiB";
     if (p.storage != LB_F64 && p.storage != LB_F32) return "storage form not implemented (LB_F64 and LB_F32 only)";
     if (!(p.tau_b > 0.5)) return "tau_b must exceed 1/2";
     if (p.rheology < 0 || p.rheology > 2) return "unknown rheology";
@@ -836,9 +838,14 @@ lb_status launch_fused(lb_handle *h, const HeadPos &H, const Box3 &head)
 {
     constexpr int TY = sizeof(R) == 8 ? TY_F64 : TY_F32;
     const Layout &L = h->L;
-    hipLaunchKernelGGL((k_fused<R, TY>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P, H, L.fg,
-                       head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
-                       as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t), h->first);
+    if (h->first)
+        hipLaunchKernelGGL((k_fused<R, TY, true>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P, H,
+                           L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
+                           as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
+    else
+        hipLaunchKernelGGL((k_fused<R, TY, false>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P,
+                           H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
+                           as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
     return check_launch(h, "k_fused");
 }
 
