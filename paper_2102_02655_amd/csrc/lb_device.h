@@ -376,12 +376,15 @@ __device__ __forceinline__ BulkIdx bulk_index(const DevParams &P, int x, int y, 
     return b;
 }
 
-// mom_add over all links of loaded values
+// mom_add over all links of loaded values, one link at a time: the barrier
+// keeps the scheduler from converting every loaded value to FP64 up front
+// (76 registers) before the mass sums consume them.
 template <typename R, bool FULL, int I = 0>
 __device__ __forceinline__ void mom_add_all(Mom<R> &M, const R (&vT)[lbq::Q], const R (&vY)[lbq::Q])
 {
     if constexpr (I < lbq::Q) {
         mom_add<R, I, FULL>(M, vT[I], vY[I]);
+        __builtin_amdgcn_sched_barrier(0);
         mom_add_all<R, FULL, I + 1>(M, vT, vY);
     }
 }

@@ -274,4 +274,244 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos
     }
 }
 
+// Producer/consumer form of the march.  Waves 0 .. TY + 2 are loaders (the
+// tile rows, the two ring rows, the two ring columns as above): they pull and
+// reduce plane p, keeping the loads of plane p + 1 in flight meanwhile (FP32),
+// and write the colour fields and the tile cells' raw moments to LDS.
+// Waves TY + 3 .. 2 TY + 2 are colliders, one per tile row: in the same
+// iteration they take plane p - 2 (stencil planes p - 3 .. p - 1, all reduced
+// in earlier iterations) from its moments to its 38 stored values, the local
+// relaxation time included.  One barrier per
+// plane.  Loads and stores are issued by different waves, so neither waits
+// behind the other in a wave's queue of outstanding memory operations.
+template <typename R, int TY, bool FIRST>
+__global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, HeadPos H, FusedGrid FG, Box3 head,
+                                                                  const R *__restrict__ src, R *__restrict__ dst,
+                                                                  const double *__restrict__ momd,
+                                                                  const R *__restrict__ mom,
+                                                                  const R *__restrict__ chi,
+                                                                  const R *__restrict__ ghost,
+                                                                  R *__restrict__ mac_next)
+{
+    constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
+    constexpr bool DEEP = sizeof(R) == 4;
+    __shared__ R chi_l[4][3][PL];
+    __shared__ double mo_d[4][2][NI];      // masses delta rho, rho_Y (FP64)
+    __shared__ R mo_r[4][NMOMR][NI];       // the other raw moments m[2..16]
+    __shared__ unsigned char st_ok[4][NI];
+
+    const int nb = gridDim.x;
+    const int b = blockIdx.x;
+    const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int tx = t % FG.ntx, ty = (t / FG.ntx) % FG.nty, tz = t / (FG.ntx * FG.nty);
+    const int x0 = tx * 64, y0 = ty * TY, z0 = tz * FG.zlen;
+    const int z1 = min(z0 + FG.zlen, P.nz);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long N = P.N;
+    const long long plane_sz = (long long)P.nx * P.ny;
+    const unsigned long long pstride = (unsigned long long)N * sizeof(R);
+
+    if (wave >= TY + 3) {
+        // ---------------- collider: tile row wave - TY - 3
+        const int r = wave - (TY + 3);
+        const int cx = x0 + lane, cy = y0 + r;
+        const bool tile = cx < P.nx && cy < P.ny;
+        const int xw = wrap_any(cx, P.nx), yw = wrap_any(cy, P.ny);
+        const int row = r + 1, col = lane + 1;
+        const int ii = r * 64 + lane;
+        const long long col_off = (long long)yw * P.nx + xw;
+        for (int p = z0 - 1; p <= z1 + 1; ++p) {
+            const int c = p - 2;
+            if (tile && c >= z0 && st_ok[c & 3][ii]) {
+                const int ss = c & 3;
+                const int sm = (c + 3) & 3, s0 = c & 3, sp1 = (c + 1) & 3;
+                Grad<R> G;
+#pragma unroll
+                for (int m = 0; m < 9; ++m) G.g[m] = R(0);
+#pragma unroll
+                for (int i = 1; i < lbq::Q; i += 2) {
+                    const int X = lbq::cx(i), Yc = lbq::cy(i), Z = lbq::cz(i);
+                    const int sa = Z > 0 ? sp1 : (Z < 0 ? sm : s0);
+                    const int sb = Z > 0 ? sm : (Z < 0 ? sp1 : s0);
+                    const int la = (row + Yc) * W + col + X, lb = (row - Yc) * W + col - X;
+                    const R kk = R(3.0 * lbq::w(i));
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        const R d = kk * (chi_l[sa][f][la] - chi_l[sb][f][lb]);
+                        if (X) G.g[3 * f + 0] += X > 0 ? d : -d;
+                        if (Yc) G.g[3 * f + 1] += Yc > 0 ? d : -d;
+                        if (Z) G.g[3 * f + 2] += Z > 0 ? d : -d;
+                    }
+                }
+                Mom<R> M;
+                M.dm[0] = mo_d[ss][0][ii];
+                M.dm[1] = mo_d[ss][1][ii];
+#pragma unroll
+                for (int m = 2; m < NMOM; ++m) M.m[m] = mo_r[ss][m - 2][ii];
+                const CellState<R> C = cell_state<R>(P, M);
+                const long long ccell = col_off + (long long)c * plane_sz;
+                R rY, rB, u[3];
+                collide_state<R>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,
+                                 (unsigned)(ccell * (long long)sizeof(R)), rY, rB, u);
+                if (macro_needed(P, H, xw, yw, c)) {
+                    mac_next[ccell] = rY;
+                    mac_next[N + ccell] = rB;
+                    mac_next[2 * N + ccell] = u[0];
+                    mac_next[3 * N + ccell] = u[1];
+                    mac_next[4 * N + ccell] = u[2];
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    // ---------------- loader: tile row, ring row or ring columns
+    int cx, cy, row, col;
+    bool active = true;
+    if (wave < TY) {
+        cx = x0 + lane;
+        cy = y0 + wave;
+        row = wave + 1;
+        col = lane + 1;
+    } else if (wave == TY) {
+        cx = x0 + lane;
+        cy = y0 - 1;
+        row = 0;
+        col = lane + 1;
+    } else if (wave == TY + 1) {
+        cx = x0 + lane;
+        cy = y0 + TY;
+        row = TY + 1;
+        col = lane + 1;
+    } else {
+        if (lane < HH) {
+            cx = x0 - 1;
+            cy = y0 - 1 + lane;
+            row = lane;
+            col = 0;
+        } else if (lane < 2 * HH) {
+            cx = x0 + 64;
+            cy = y0 - 1 + lane - HH;
+            row = lane - HH;
+            col = 65;
+        } else {
+            cx = x0;
+            cy = y0;
+            row = 0;
+            col = 0;
+            active = false;
+        }
+    }
+    const bool tile = active && wave < TY && cx < P.nx && cy < P.ny;
+    const int xw = wrap_any(cx, P.nx), yw = wrap_any(cy, P.ny);
+    const int lidx = row * W + col;
+    const int ii = wave * 64 + lane;
+    const bool shell_c = active && !far_from_head(P, H.hx_c, H.hy_c, xw, yw) &&
+                         column_class(P, H.hx_c, H.hy_c, xw, yw) == COL_SHELL;
+    const bool head_col = active && in_box(P, Box3{head.x0, head.y0, 0, head.w, head.h, P.nz}, xw, yw, 0);
+    const long long col_off = (long long)yw * P.nx + xw;
+
+    struct PlaneJob {
+        bool load, ghost, prep, bulk, own;
+        int zp;
+        long long cell;
+    };
+    auto job = [&](int p) {
+        PlaneJob J;
+        J.load = active && p <= z1;
+        J.zp = p;
+        J.ghost = false;
+        if (p < 0 || p >= P.nz) {
+            if (P.periodic_z)
+                J.zp = wrap_any(p, P.nz);
+            else
+                J.ghost = true;
+        }
+        J.own = tile && p >= z0 && p < z1;
+        const bool zface = !P.periodic_z && (J.zp == 0 || J.zp == P.nz - 1);
+        J.prep = J.load && !J.ghost && (zface || (head_col && J.zp >= head.z0 && J.zp < head.z0 + head.d));
+        J.bulk = J.load && !J.ghost && !J.prep;
+        J.cell = J.ghost ? 0 : col_off + (long long)J.zp * plane_sz;
+        return J;
+    };
+    auto issue = [&](int p, R(&vT)[lbq::Q], R(&vY)[lbq::Q]) {
+        const PlaneJob J = job(p);
+        if (J.bulk)
+            pull_bulk_issue<R, FIRST>(fresh_global_c(src), fresh_uniform(pstride), bulk_index<R>(P, xw, yw, J.zp),
+                                      (unsigned)(J.cell * (long long)sizeof(R)), vT, vY);
+    };
+    auto reduce = [&](int p, const R(&vT)[lbq::Q], const R(&vY)[lbq::Q]) {
+        const PlaneJob J = job(p);
+        if (!J.load) return;
+        R cN, cY, cB;
+        bool cur_ok = false;
+        if (J.ghost) {
+            const int face = p < 0 ? 0 : 1;
+            const long long gc = (long long)yw * P.nx + xw;
+            cN = ghost[(face * 3 + 0) * plane_sz + gc];
+            cY = ghost[(face * 3 + 1) * plane_sz + gc];
+            cB = ghost[(face * 3 + 2) * plane_sz + gc];
+        } else {
+            Mom<R> M;
+            mom_zero(M);
+            bool fluid = true;
+            if (J.prep) {
+                cN = chi[J.cell];
+                cY = chi[N + J.cell];
+                cB = chi[2 * N + J.cell];
+                fluid = !(shell_c && (double)J.zp >= P.tip_z);
+                if (J.own && fluid) {
+                    M.dm[0] = momd[J.cell];
+                    M.dm[1] = momd[N + J.cell];
+#pragma unroll
+                    for (int m = 2; m < NMOM; ++m) M.m[m] = mom[(m - 2) * N + J.cell];
+                }
+            } else {
+                // one code path for tile and ring cells (a branch here lets
+                // the compiler hoist all 38 FP64 conversions above it)
+                mom_add_all<R, true>(M, vT, vY);
+                chi_of<R>(P, R(M.dm[1]), R(P.rho_ref + M.dm[0] - M.dm[1]), cN, cY, cB);
+            }
+            if (J.own && fluid) {
+                const int ss = p & 3;
+                mo_d[ss][0][ii] = M.dm[0];
+                mo_d[ss][1][ii] = M.dm[1];
+#pragma unroll
+                for (int m = 2; m < NMOM; ++m) mo_r[ss][m - 2][ii] = M.m[m];
+                cur_ok = true;
+            }
+        }
+        const int cs = p & 3;
+        chi_l[cs][0][lidx] = cN;
+        chi_l[cs][1][lidx] = cY;
+        chi_l[cs][2][lidx] = cB;
+        if (wave < TY) st_ok[p & 3][ii] = cur_ok ? 1 : 0;
+    };
+
+    R aT[lbq::Q], aY[lbq::Q];
+    if constexpr (!DEEP) {
+        for (int p = z0 - 1; p <= z1 + 1; ++p) {
+            issue(p, aT, aY);
+            __builtin_amdgcn_sched_barrier(0);
+            reduce(p, aT, aY);
+            __syncthreads();
+        }
+        return;
+    }
+    R bT[lbq::Q], bY[lbq::Q];
+    issue(z0 - 1, aT, aY);
+    for (int p = z0 - 1; p <= z1 + 1; p += 2) {
+        issue(p + 1, bT, bY);
+        __builtin_amdgcn_sched_barrier(0);
+        reduce(p, aT, aY);
+        __syncthreads();
+        if (p + 1 > z1 + 1) break;
+        issue(p + 2, aT, aY);
+        __builtin_amdgcn_sched_barrier(0);
+        reduce(p + 1, bT, bY);
+        __syncthreads();
+    }
+}
+
 }  // namespace lbk

@@ -838,14 +838,28 @@ lb_status launch_fused(lb_handle *h, const HeadPos &H, const Box3 &head)
 {
     constexpr int TY = sizeof(R) == 8 ? TY_F64 : TY_F32;
     const Layout &L = h->L;
-    if (h->first)
-        hipLaunchKernelGGL((k_fused<R, TY, true>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P, H,
-                           L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
-                           as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
-    else
-        hipLaunchKernelGGL((k_fused<R, TY, false>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P,
-                           H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
-                           as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
+    if constexpr (sizeof(R) == 4) {
+        if (h->first)
+            hipLaunchKernelGGL((k_fused_pc<R, TY, true>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
+                               h->stream, h->P, H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
+                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
+                               mac_at<R>(h, h->t));
+        else
+            hipLaunchKernelGGL((k_fused_pc<R, TY, false>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
+                               h->stream, h->P, H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
+                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
+                               mac_at<R>(h, h->t));
+    } else {
+        if (h->first)
+            hipLaunchKernelGGL((k_fused<R, TY, true>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P,
+                               H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
+                               as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
+        else
+            hipLaunchKernelGGL((k_fused<R, TY, false>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream,
+                               h->P, H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
+                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
+                               mac_at<R>(h, h->t));
+    }
     return check_launch(h, "k_fused");
 }
 
