@@ -486,8 +486,9 @@ FusedGrid fused_grid(const lb_params &p, int ty)
     g.ntx = (p.nx + 63) / 64;
     g.nty = (p.ny + ty - 1) / ty;
     long long tiles = (long long)g.ntx * g.nty;
-    // enough blocks for two per CU on 256 CUs, z chunks of at least 8 planes
-    long long want = (1024 + tiles - 1) / tiles;
+    // one resident block per CU: about two rounds of blocks on 256 CUs, z
+    // chunks of at least 8 planes (long chunks spend fewer halo planes)
+    long long want = (512 + tiles - 1) / tiles;
     long long maxc = std::max(1, p.nz / 8);
     g.nzc = (int)std::max(1LL, std::min(want, maxc));
     if (const char *e = std::getenv("LBPRINT_ZLEN")) {
