@@ -132,6 +132,21 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
  * LB_ESTATE after an LB_EUNSTABLE result. */
 lb_status lb_step(lb_handle *h, int nsteps);
 
+/* Batched stepping: advance handle hs[i] by nsteps[i] steps, i = 0 .. n-1
+ * (distinct handles on one device; any mix of sizes, storage forms and
+ * parameters; check_interval must be 0).  A handle's first step and an odd
+ * remainder run as ordinary launches on its own stream; the even part of
+ * every handle runs in ONE graph launch on hs[0]'s stream, each handle's
+ * steps a captured chain of kernels (an independent branch of the graph, so
+ * the handles' work overlaps on the device).  Chains and instantiated batch
+ * graphs are cached and replayed while the same handles are stepped by the
+ * same counts; a handle's cached graphs are released by lb_destroy.  Work is
+ * ordered after earlier work on every handle's stream and before later work
+ * on it (events).  The result of every handle is bit-identical to stepping
+ * it alone with lb_step.  Asynchronous; LB_EINVAL on bad arguments,
+ * LB_ESTATE on an unstable handle, LB_EDEVICE if a graph call fails. */
+lb_status lb_step_batch(lb_handle *const *hs, const int *nsteps, int n);
+
 /* Fields and conserved sums at the current step.  rho_y, rho_b (N values) and
  * u (3N values, the physical velocity (sum f c + F/2) / rho) are written as
  * FP64 (dtype 0) or FP32 (dtype 1) into host (dst_is_device = 0) or device

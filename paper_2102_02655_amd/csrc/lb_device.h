@@ -67,6 +67,7 @@ struct DevParams {
     int has_nozzle;
     double ri2, ro2, rout, tip_z;
     double vnoz[2];
+    double x0noz[2];           // head axis (x, y) at t = 0
     double u_in[3];            // u_ink + v_nozzle, Eq. (movnozzle)
     double lid_rho;
 };

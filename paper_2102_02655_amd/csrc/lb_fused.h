@@ -37,6 +37,87 @@ struct Box3 {
     int x0, y0, z0, w, h, d;
 };
 
+// Geometry of one time step (from step t to t + 1), a function of t alone:
+// the head axis at t - 1 and t (Sec. II.B, x_h(t) = x_h(0) + v t), the head's
+// box (cells its template can touch between the two positions, two cells of
+// margin, from the tip plane up) and the boxes of cells whose pull touches a
+// boundary.  It lives in device memory, written by a one-thread kernel at the
+// start of every step from a device step counter, so that the launches of a
+// step have the same arguments at every step (a captured multi-step graph
+// replays correctly).
+struct StepGeom {
+    long long t;  // steps completed
+    int first;    // no step taken yet
+    int nbox;     // boundary-preparation boxes in use
+    HeadPos H;
+    Box3 hb;      // head box
+    Box3 bx[3];   // boundary-preparation boxes: head box one plane deeper, z = 0, z = nz - 1
+};
+
+// Head axis at step t, wrapped into [0, n); also the unwrapped position.
+// Rounded as written (no contraction), identical on host and device.
+__host__ __device__ inline void head_axis(const DevParams &P, long long t, double &hx, double &hy, double &ux,
+                                          double &uy)
+{
+#pragma clang fp contract(off)
+    const double x = P.x0noz[0] + P.vnoz[0] * (double)t;
+    const double y = P.x0noz[1] + P.vnoz[1] * (double)t;
+    ux = x;
+    uy = y;
+    hx = x - (double)P.nx * floor(x / (double)P.nx);
+    hy = y - (double)P.ny * floor(y / (double)P.ny);
+}
+
+__host__ __device__ inline void make_geom(const DevParams &P, long long t, int first, StepGeom &g)
+{
+#pragma clang fp contract(off)
+    g.t = t;
+    g.first = first;
+    double uxc = 0, uyc = 0, uxp = 0, uyp = 0;
+    g.H.hx_c = g.H.hy_c = g.H.hx_p = g.H.hy_p = 0.0;
+    if (P.has_nozzle) {
+        head_axis(P, t, g.H.hx_c, g.H.hy_c, uxc, uyc);
+        if (first) {
+            g.H.hx_p = g.H.hx_c;
+            g.H.hy_p = g.H.hy_c;
+            uxp = uxc;
+            uyp = uyc;
+        } else {
+            head_axis(P, t - 1, g.H.hx_p, g.H.hy_p, uxp, uyp);
+        }
+    }
+    g.hb = Box3{0, 0, 0, 0, 0, 0};
+    g.nbox = 1;
+    g.bx[0] = g.bx[1] = g.bx[2] = Box3{0, 0, 0, 0, 0, 0};
+    if (P.has_nozzle) {
+        const double r = P.rout + 2.0;
+        const double xl = fmin(uxp, uxc), xh = fmax(uxp, uxc), yl = fmin(uyp, uyc), yh = fmax(uyp, uyc);
+        Box3 b;
+        b.x0 = (int)floor(xl - r);
+        b.y0 = (int)floor(yl - r);
+        b.w = (int)ceil(xh + r) - b.x0 + 1;
+        b.h = (int)ceil(yh + r) - b.y0 + 1;
+        if (b.w > P.nx) {
+            b.w = P.nx;
+            b.x0 = 0;
+        }
+        if (b.h > P.ny) {
+            b.h = P.ny;
+            b.y0 = 0;
+        }
+        b.z0 = (int)floor(P.tip_z);
+        if (b.z0 < 0) b.z0 = 0;
+        b.d = P.nz - b.z0;
+        g.hb = b;
+        const int z0 = b.z0 - 1 > 0 ? b.z0 - 1 : 0;
+        g.bx[0] = Box3{b.x0, b.y0, z0, b.w, b.h, P.nz - z0};
+    }
+    if (!P.periodic_z) {
+        g.bx[g.nbox++] = Box3{0, 0, 0, P.nx, P.ny, 1};
+        if (P.nz > 1) g.bx[g.nbox++] = Box3{0, 0, P.nz - 1, P.nx, P.ny, 1};
+    }
+}
+
 // Cells whose pull touches a boundary (a z face or the head) are pulled with
 // the boundary rules by the preparation kernel; every other cell has only
 // fluid sources.
@@ -75,13 +156,16 @@ __device__ __forceinline__ bool macro_needed(const DevParams &P, const HeadPos &
 }
 
 template <typename R, int TY, bool FIRST>
-__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos H, FusedGrid FG, Box3 head,
-                                                            const R *__restrict__ src, R *__restrict__ dst,
+__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, const StepGeom *__restrict__ G,
+                                                            FusedGrid FG, const R *__restrict__ src,
+                                                            R *__restrict__ dst,
                                                             const double *__restrict__ momd,
                                                             const R *__restrict__ mom, const R *__restrict__ chi,
                                                             const R *__restrict__ ghost, R *__restrict__ mac_next)
 {
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
+    const HeadPos H = G->H;
+    const Box3 head = G->bx[0];
     __shared__ R chi_l[4][3][PL];
     __shared__ double st_d[2][2][NI];
     __shared__ R st_r[2][10][NI];
@@ -285,8 +369,9 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, HeadPos
 // plane.  Loads and stores are issued by different waves, so neither waits
 // behind the other in a wave's queue of outstanding memory operations.
 template <typename R, int TY, bool FIRST>
-__global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, HeadPos H, FusedGrid FG, Box3 head,
-                                                                  const R *__restrict__ src, R *__restrict__ dst,
+__global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, const StepGeom *__restrict__ G,
+                                                                  FusedGrid FG, const R *__restrict__ src,
+                                                                  R *__restrict__ dst,
                                                                   const double *__restrict__ momd,
                                                                   const R *__restrict__ mom,
                                                                   const R *__restrict__ chi,
@@ -295,6 +380,8 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
 {
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     constexpr bool DEEP = sizeof(R) == 4;
+    const HeadPos H = G->H;
+    const Box3 head = G->bx[0];
     __shared__ R chi_l[4][3][PL];
     __shared__ double mo_d[4][2][NI];      // masses delta rho, rho_Y (FP64)
     __shared__ R mo_r[4][NMOMR][NI];       // the other raw moments m[2..16]

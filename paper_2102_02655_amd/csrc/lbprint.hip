@@ -19,6 +19,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <mutex>
 #include <algorithm>
 
 #include "../../include/lbprint.h"
@@ -99,10 +100,11 @@ __device__ __forceinline__ void dens(const DevParams &P, const double *__restric
 
 // Initial state: f^k = f^{k,eq}(rho^k, u) at the fluid cells of step 0.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_init(DevParams P, HeadPos H, const double *__restrict__ rho_y,
-                                              const double *__restrict__ rho_b, const double *__restrict__ u,
-                                              int has_u, R *__restrict__ dst)
+__global__ __launch_bounds__(TPB) void k_init(DevParams P, const StepGeom *__restrict__ G,
+                                              const double *__restrict__ rho_y, const double *__restrict__ rho_b,
+                                              const double *__restrict__ u, int has_u, R *__restrict__ dst)
 {
+    const HeadPos H = G->H;
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     if (cell >= P.N) return;
     int x, y, z;
@@ -169,11 +171,12 @@ __device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &
 // Whole-box pull + moments (read-out path): writes this step's pending
 // boundary fluxes and deleted mass per block, touching no cumulative state.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R *__restrict__ src,
-                                                 const R *__restrict__ mac, double *__restrict__ momd,
-                                                 R *__restrict__ mom, R *__restrict__ chi, double *__restrict__ slots,
-                                                 int first)
+__global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__restrict__ G,
+                                                 const R *__restrict__ src, const R *__restrict__ mac,
+                                                 double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
+                                                 double *__restrict__ slots, int first)
 {
+    const HeadPos H = G->H;
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
     int any = 0;
@@ -193,11 +196,14 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, HeadPos H, const R
 // block's cumulative slot.  Boxes 1 and 2 skip cells of box 0 (the head box)
 // so that no cell is counted twice.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_pre(DevParams P, HeadPos H, Box3 b0, Box3 b1, Box3 b2, int nbox,
+__global__ __launch_bounds__(TPB) void k_pre(DevParams P, const StepGeom *__restrict__ G,
                                              const R *__restrict__ src, const R *__restrict__ mac,
                                              double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
                                              double *__restrict__ slots, int first)
 {
+    const HeadPos H = G->H;
+    const Box3 b0 = G->bx[0], b1 = G->bx[1], b2 = G->bx[2];
+    const int nbox = G->nbox;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
     int any = 0;
     for (int bi = 0; bi < nbox; ++bi) {
@@ -220,10 +226,12 @@ __global__ __launch_bounds__(TPB) void k_pre(DevParams P, HeadPos H, Box3 b0, Bo
 // neighbours fluid at both steps (pure air rho_B^0 if there is none).  Only
 // the moment set and the colour fields are needed downstream.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0, int by0, int bz0, int bw, int bh,
-                                                int bd, double *__restrict__ momd, R *__restrict__ mom,
-                                                R *__restrict__ chi, double *__restrict__ slots, int commit)
+__global__ __launch_bounds__(TPB) void k_create(DevParams P, const StepGeom *__restrict__ G,
+                                                double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
+                                                double *__restrict__ slots, int commit)
 {
+    const HeadPos H = G->H;
+    const int bx0 = G->hb.x0, by0 = G->hb.y0, bz0 = G->hb.z0, bw = G->hb.w, bh = G->hb.h, bd = G->hb.d;
     double acc[2] = {0.0, 0.0};
     const long long total = (long long)bw * bh * bd;
     for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
@@ -269,9 +277,11 @@ __global__ __launch_bounds__(TPB) void k_create(DevParams P, HeadPos H, int bx0,
 // Fictitious densities of the head's solid cells that touch fluid, Eq. (wet):
 // rho_s^k = zeta^k sum_i w_i s_i rho^k(x + c_i) / sum_i w_i s_i.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_wall(DevParams P, HeadPos H, int bx0, int by0, int bz0, int bw, int bh,
-                                              int bd, const double *__restrict__ momd, R *__restrict__ chi)
+__global__ __launch_bounds__(TPB) void k_wall(DevParams P, const StepGeom *__restrict__ G,
+                                              const double *__restrict__ momd, R *__restrict__ chi)
 {
+    const HeadPos H = G->H;
+    const int bx0 = G->hb.x0, by0 = G->hb.y0, bz0 = G->hb.z0, bw = G->hb.w, bh = G->hb.h, bd = G->hb.d;
     const long long total = (long long)bw * bh * bd;
     for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
         int ix = (int)(k % bw), iy = (int)((k / bw) % bh), iz = (int)(k / ((long long)bw * bh));
@@ -304,9 +314,10 @@ __global__ __launch_bounds__(TPB) void k_wall(DevParams P, HeadPos H, int bx0, i
 // layer, pressure faces their imposed densities, the inlet lid pure ink, the
 // head's shell columns above the top the nozzle's fictitious densities.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const double *__restrict__ momd,
-                                               R *__restrict__ ghost)
+__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, const StepGeom *__restrict__ G,
+                                               const double *__restrict__ momd, R *__restrict__ ghost)
 {
+    const HeadPos H = G->H;
     long long plane = (long long)P.nx * P.ny;
     long long k = (long long)blockIdx.x * TPB + threadIdx.x;
     if (k >= 2 * plane) return;
@@ -364,10 +375,12 @@ __global__ __launch_bounds__(TPB) void k_ghost(DevParams P, HeadPos H, const dou
 // Fields for lb_moments: rho_Y, rho_B, physical velocity (j + F/2)/rho; block
 // sums of mass and momentum; instability flag.
 template <typename R, typename O>
-__global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const double *__restrict__ momd,
-                                                const R *__restrict__ mom, O *__restrict__ ory, O *__restrict__ orb,
-                                                O *__restrict__ ou, double *__restrict__ part)
+__global__ __launch_bounds__(TPB) void k_output(DevParams P, const StepGeom *__restrict__ G,
+                                                const double *__restrict__ momd, const R *__restrict__ mom,
+                                                O *__restrict__ ory, O *__restrict__ orb, O *__restrict__ ou,
+                                                double *__restrict__ part)
 {
+    const HeadPos H = G->H;
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NPART] = {0, 0, 0, 0, 0, 0};
     if (cell < P.N) {
@@ -409,6 +422,25 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, HeadPos H, const do
 // Committed boundary fluxes live in the fused kernel's block slots, committed
 // deleted / created mass in the boundary kernels' slots; pend / pendc hold
 // the read-out's not-yet-committed values of the current step.
+// The step's geometry from the device step counter (one thread).
+__global__ void k_clock(DevParams P, StepGeom *__restrict__ G)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        StepGeom g;
+        make_geom(P, G->t, G->first, g);
+        *G = g;
+    }
+}
+
+// End of a step: advance the device step counter.
+__global__ void k_tick(StepGeom *__restrict__ G)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        G->t += 1;
+        G->first = 0;
+    }
+}
+
 __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part, const double *__restrict__ pend,
                                                 long long nbm, const double *__restrict__ cumpre, int nbp,
                                                 const double *__restrict__ cumc, const double *__restrict__ pendc,
@@ -466,11 +498,12 @@ constexpr size_t ALIGN = 256;
 size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-    size_t pops, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, total;
+    size_t pops, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, geo, total;
     long long nbm;   // blocks of the whole-box read-out kernels
     FusedGrid fg;    // tiling of the fused step kernel
     long long nbf;   // its block count
     int ty;          // its tile height
+    unsigned nb_wall;  // blocks of the wall-density kernel (grid-stride over the head box)
 };
 
 size_t real_size(int storage) { return storage == LB_F64 ? 8 : 4; }
@@ -508,6 +541,13 @@ Layout layout_of(const lb_params &p)
     L.nbm = (N + TPB - 1) / TPB;
     L.ty = p.storage == LB_F64 ? TY_F64 : TY_F32;
     L.fg = fused_grid(p, L.ty);
+    {
+        // the head box spans at most 2 (r_out + 2) + 4 columns each way
+        long long wmax = p.has_nozzle ? 2 * (long long)std::ceil(p.noz_r_in + p.noz_wall + 2.0) + 4 : 0;
+        long long bw = std::min<long long>(wmax, p.nx), bh = std::min<long long>(wmax, p.ny);
+        long long tot = bw * bh * p.nz;
+        L.nb_wall = (unsigned)std::max<long long>(1, std::min<long long>((tot + TPB - 1) / TPB, 4096));
+    }
     L.nbf = (long long)L.fg.ntx * L.fg.nty * L.fg.nzc;
     size_t off = 0;
     L.pops = off;
@@ -534,6 +574,8 @@ Layout layout_of(const lb_params &p)
     off += al(NB_SPARSE * 2 * 8);
     L.red = off;
     off += al(16 * 8);
+    L.geo = off;
+    off += al(sizeof(StepGeom));
     L.total = off;
     return L;
 }
@@ -642,25 +684,14 @@ DevParams make_dev(const lb_params &p)
         P.tip_z = p.noz_tip_z;
         P.vnoz[0] = p.noz_v[0];
         P.vnoz[1] = p.noz_v[1];
+        P.x0noz[0] = p.noz_x0[0];
+        P.x0noz[1] = p.noz_x0[1];
         P.u_in[0] = p.u_ink[0] + p.noz_v[0];
         P.u_in[1] = p.u_ink[1] + p.noz_v[1];
         P.u_in[2] = p.u_ink[2];
         P.lid_rho = p.lid_rho_y;
     }
     return P;
-}
-
-// Head axis at step t: x = x0 + v t, wrapped into [0, n).  Rounded as
-// written (no contraction) so every implementation rasterises identically.
-void head_at(const lb_params &p, long t, double *hx, double *hy, double *ux, double *uy)
-{
-#pragma clang fp contract(off)
-    double x = p.noz_x0[0] + p.noz_v[0] * (double)t;
-    double y = p.noz_x0[1] + p.noz_v[1] * (double)t;
-    *ux = x;
-    *uy = y;
-    *hx = x - (double)p.nx * std::floor(x / (double)p.nx);
-    *hy = y - (double)p.ny * std::floor(y / (double)p.ny);
 }
 
 }  // namespace
@@ -682,9 +713,22 @@ struct lb_handle {
     size_t nev = 0;
     double acc_step = 0.0, acc_prep = 0.0;
     long acc_n = 0;
+    // batched stepping (lb_step_batch): captured k-step chains, keyed by
+    // (k, population buffer, step parity), a private capture stream and an
+    // event for cross-stream ordering
+    struct Chain {
+        int k, cur, parity;
+        hipGraph_t g;
+    };
+    std::vector<Chain> chains;
+    hipStream_t cap = nullptr;
+    hipEvent_t sync_ev = nullptr;
     ~lb_handle()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        for (Chain &c : chains) (void)hipGraphDestroy(c.g);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (sync_ev) (void)hipEventDestroy(sync_ev);
     }
 };
 
@@ -710,58 +754,19 @@ R *as(lb_handle *h, size_t off)
     return reinterpret_cast<R *>(h->ws + off);
 }
 
-HeadPos heads(const lb_handle *h, double *bx_lo, double *bx_hi, double *by_lo, double *by_hi)
-{
-    HeadPos H;
-    double ux_c = 0, uy_c = 0, ux_p = 0, uy_p = 0;
-    head_at(h->p, h->t, &H.hx_c, &H.hy_c, &ux_c, &uy_c);
-    if (h->first) {
-        H.hx_p = H.hx_c;
-        H.hy_p = H.hy_c;
-        ux_p = ux_c;
-        uy_p = uy_c;
-    } else {
-        head_at(h->p, h->t - 1, &H.hx_p, &H.hy_p, &ux_p, &uy_p);
-    }
-    if (bx_lo) {
-        *bx_lo = std::fmin(ux_p, ux_c);
-        *bx_hi = std::fmax(ux_p, ux_c);
-        *by_lo = std::fmin(uy_p, uy_c);
-        *by_hi = std::fmax(uy_p, uy_c);
-    }
-    return H;
-}
-
-struct Box {
-    int x0, y0, z0, w, h, d;
-};
-
-Box head_box(const lb_handle *h, double xlo, double xhi, double ylo, double yhi)
-{
-    Box b;
-    double r = h->P.rout + 2.0;
-    b.x0 = (int)std::floor(xlo - r);
-    b.y0 = (int)std::floor(ylo - r);
-    b.w = (int)std::ceil(xhi + r) - b.x0 + 1;
-    b.h = (int)std::ceil(yhi + r) - b.y0 + 1;
-    if (b.w > h->p.nx) {
-        b.w = h->p.nx;
-        b.x0 = 0;
-    }
-    if (b.h > h->p.ny) {
-        b.h = h->p.ny;
-        b.y0 = 0;
-    }
-    b.z0 = (int)std::floor(h->P.tip_z);
-    if (b.z0 < 0) b.z0 = 0;
-    b.d = h->p.nz - b.z0;
-    return b;
-}
-
 template <typename R>
 R *pops_at(lb_handle *h, int which)
 {
     return as<R>(h, h->L.pops + which * al(2 * lbq::Q * (size_t)h->P.N * sizeof(R)));
+}
+
+StepGeom *geo(lb_handle *h) { return as<StepGeom>(h, h->L.geo); }
+
+// The step's geometry from the device step counter.
+lb_status launch_clock(lb_handle *h)
+{
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, h->stream, h->P, geo(h));
+    return check_launch(h, "k_clock");
 }
 
 // macro buffer written at step t is t & 1; the pull of step t reads (t - 1) & 1
@@ -776,17 +781,15 @@ R *mac_at(lb_handle *h, long t)
 template <typename R>
 lb_status run_readout(lb_handle *h)
 {
-    double xl, xh, yl, yh;
-    HeadPos H = heads(h, &xl, &xh, &yl, &yh);
     const Layout &L = h->L;
-    hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, H, pops_at<R>(h, h->cur),
-                       mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
-                       as<double>(h, L.pend), h->first);
+    if (lb_status s = launch_clock(h)) return s;
+    hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
+                       pops_at<R>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
+                       as<R>(h, L.chi), as<double>(h, L.pend), h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
-        Box b = head_box(h, xl, xh, yl, yh);
-        hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, H, b.x0, b.y0, b.z0, b.w, b.h,
-                           b.d, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.pendc), 0);
+        hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, geo(h),
+                           as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.pendc), 0);
         if (lb_status s = check_launch(h, "k_create")) return s;
     } else {
         if (hipMemsetAsync(as<double>(h, L.pendc), 0, NB_SPARSE * 2 * 8, h->stream) != hipSuccess)
@@ -835,85 +838,74 @@ lb_status timing_mark(lb_handle *h, int k)
 }
 
 template <typename R>
-lb_status launch_fused(lb_handle *h, const HeadPos &H, const Box3 &head)
+lb_status launch_fused(lb_handle *h)
 {
     constexpr int TY = sizeof(R) == 8 ? TY_F64 : TY_F32;
     const Layout &L = h->L;
     if constexpr (sizeof(R) == 4) {
         if (h->first)
             hipLaunchKernelGGL((k_fused_pc<R, TY, true>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
-                               h->stream, h->P, H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
+                               h->stream, h->P, geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
                                as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
                                mac_at<R>(h, h->t));
         else
             hipLaunchKernelGGL((k_fused_pc<R, TY, false>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
-                               h->stream, h->P, H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
+                               h->stream, h->P, geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
                                as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
                                mac_at<R>(h, h->t));
     } else {
         if (h->first)
             hipLaunchKernelGGL((k_fused<R, TY, true>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P,
-                               H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
+                               geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
                                as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
         else
             hipLaunchKernelGGL((k_fused<R, TY, false>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream,
-                               h->P, H, L.fg, head, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
+                               h->P, geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
                                as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
                                mac_at<R>(h, h->t));
     }
     return check_launch(h, "k_fused");
 }
 
-// One time step: boundary preparation (pulls of the cells next to the z faces
-// and the head, node creation, wall densities, ghost layers), then the fused
-// step kernel over the whole box.
+// One time step: the step's geometry, boundary preparation (pulls of the
+// cells next to the z faces and the head, node creation, wall densities,
+// ghost layers), the fused step kernel over the whole box, the step counter.
+// Every launch argument is the same at every step of one parity (the
+// population and macro buffers alternate), so an even number of steps can be
+// captured once and replayed.
 template <typename R>
 lb_status run_step(lb_handle *h)
 {
-    double xl, xh, yl, yh;
-    HeadPos H = heads(h, &xl, &xh, &yl, &yh);
     const Layout &L = h->L;
-    Box3 bx[3] = {{0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}, {0, 0, 0, 0, 0, 0}};
-    Box hb = {0, 0, 0, 0, 0, 0};
     if (lb_status s = timing_mark(h, 0)) return s;
-    if (h->p.has_nozzle) {
-        hb = head_box(h, xl, xh, yl, yh);
-        int z0 = std::max(0, hb.z0 - 1);
-        bx[0] = Box3{hb.x0, hb.y0, z0, hb.w, hb.h, h->p.nz - z0};
-    }
-    int nbox = 1;
-    if (!h->P.periodic_z) {
-        bx[nbox++] = Box3{0, 0, 0, h->p.nx, h->p.ny, 1};
-        if (h->p.nz > 1) bx[nbox++] = Box3{0, 0, h->p.nz - 1, h->p.nx, h->p.ny, 1};
-    }
+    if (lb_status s = launch_clock(h)) return s;
     if (h->p.has_nozzle || !h->P.periodic_z) {
-        hipLaunchKernelGGL(k_pre<R>, dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, H, bx[0], bx[1], bx[2], nbox,
-                           pops_at<R>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
-                           as<R>(h, L.chi), as<double>(h, L.cumpre), h->first);
+        hipLaunchKernelGGL(k_pre<R>, dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, geo(h), pops_at<R>(h, h->cur),
+                           mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                           as<double>(h, L.cumpre), h->first);
         if (lb_status s = check_launch(h, "k_pre")) return s;
     }
     if (h->p.has_nozzle) {
         if (!h->first) {
-            hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, H, hb.x0, hb.y0, hb.z0,
-                               hb.w, hb.h, hb.d, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
-                               as<double>(h, L.cumc), 1);
+            hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, geo(h),
+                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.cumc), 1);
             if (lb_status s = check_launch(h, "k_create")) return s;
         }
-        long long tot = (long long)hb.w * hb.h * hb.d;
-        unsigned nb = (unsigned)std::min<long long>((tot + TPB - 1) / TPB, 4096);
-        hipLaunchKernelGGL(k_wall<R>, dim3(nb), dim3(TPB), 0, h->stream, h->P, H, hb.x0, hb.y0, hb.z0, hb.w, hb.h,
-                           hb.d, as<double>(h, L.momd), as<R>(h, L.chi));
+        hipLaunchKernelGGL(k_wall<R>, dim3(L.nb_wall), dim3(TPB), 0, h->stream, h->P, geo(h), as<double>(h, L.momd),
+                           as<R>(h, L.chi));
         if (lb_status s = check_launch(h, "k_wall")) return s;
     }
     if (!h->P.periodic_z) {
         long long n = 2LL * h->p.nx * h->p.ny;
-        hipLaunchKernelGGL(k_ghost<R>, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, h->stream, h->P, H,
+        hipLaunchKernelGGL(k_ghost<R>, dim3((unsigned)((n + TPB - 1) / TPB)), dim3(TPB), 0, h->stream, h->P, geo(h),
                            as<double>(h, L.momd), as<R>(h, L.ghost));
         if (lb_status s = check_launch(h, "k_ghost")) return s;
     }
     if (lb_status s = timing_mark(h, 1)) return s;
-    if (lb_status s = launch_fused<R>(h, H, bx[0])) return s;
+    if (lb_status s = launch_fused<R>(h)) return s;
     if (lb_status s = timing_mark(h, 2)) return s;
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, h->stream, geo(h));
+    if (lb_status s = check_launch(h, "k_tick")) return s;
     h->cur = 1 - h->cur;
     h->t += 1;
     h->first = 0;
@@ -923,8 +915,7 @@ lb_status run_step(lb_handle *h)
 template <typename R, typename O>
 lb_status run_output(lb_handle *h, O *ry, O *rb, O *u)
 {
-    HeadPos H = heads(h, nullptr, nullptr, nullptr, nullptr);
-    hipLaunchKernelGGL((k_output<R, O>), dim3((unsigned)h->L.nbm), dim3(TPB), 0, h->stream, h->P, H,
+    hipLaunchKernelGGL((k_output<R, O>), dim3((unsigned)h->L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
                        as<double>(h, h->L.momd), as<R>(h, h->L.mom), ry, rb, u, as<double>(h, h->L.part));
     return check_launch(h, "k_output");
 }
@@ -981,6 +972,138 @@ lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, i
     return LB_OK;
 }
 
+// ---------------------------------------------------------------- batching
+
+// k steps of one handle captured as a graph (k even: the buffers a step uses
+// depend on the step's parity only, so the chain replays correctly for as
+// long as the handle's parity and population buffer match the key).
+lb_status chain_of(lb_handle *h, int k, hipGraph_t *out)
+{
+    const int parity = (int)(h->t & 1);
+    for (const lb_handle::Chain &c : h->chains)
+        if (c.k == k && c.cur == h->cur && c.parity == parity) {
+            *out = c.g;
+            return LB_OK;
+        }
+    if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(h, LB_EDEVICE, "hipStreamCreate (capture stream)");
+    const hipStream_t saved = h->stream;
+    const int cur = h->cur, first = h->first, timing = h->timing;
+    const long t = h->t;
+    h->timing = 0;
+    if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(h, LB_EDEVICE, "hipStreamBeginCapture");
+    h->stream = h->cap;
+    lb_status st = LB_OK;
+    for (int j = 0; j < k && st == LB_OK; ++j)
+        st = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    h->stream = saved;
+    h->cur = cur;
+    h->first = first;
+    h->t = t;
+    h->timing = timing;
+    if (st != LB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess || !g) return fail(h, LB_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+    h->chains.push_back(lb_handle::Chain{k, cur, (int)(t & 1), g});
+    *out = g;
+    return LB_OK;
+}
+
+// Instantiated batch graphs: one child node per handle, no dependencies
+// between them, so the handles' chains run concurrently.
+struct BatchExec {
+    std::vector<lb_handle *> hs;
+    std::vector<int> ks, curs, parities;
+    hipGraph_t parent;
+    hipGraphExec_t exec;
+};
+std::mutex g_batch_mu;
+std::vector<BatchExec> g_batches;
+constexpr size_t MAX_BATCH_EXECS = 16;
+
+void drop_batch(BatchExec &b)
+{
+    (void)hipGraphExecDestroy(b.exec);
+    (void)hipGraphDestroy(b.parent);
+}
+
+void purge_batches(lb_handle *h)
+{
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (size_t i = 0; i < g_batches.size();) {
+        bool has = false;
+        for (lb_handle *x : g_batches[i].hs) has |= x == h;
+        if (has) {
+            drop_batch(g_batches[i]);
+            g_batches.erase(g_batches.begin() + (long)i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+lb_status batch_exec(const std::vector<lb_handle *> &hs, const std::vector<int> &ks, hipGraphExec_t *out)
+{
+    std::vector<int> curs, pars;
+    for (lb_handle *h : hs) {
+        curs.push_back(h->cur);
+        pars.push_back((int)(h->t & 1));
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (BatchExec &b : g_batches)
+        if (b.hs == hs && b.ks == ks && b.curs == curs && b.parities == pars) {
+            *out = b.exec;
+            return LB_OK;
+        }
+    hipGraph_t parent = nullptr;
+    if (hipGraphCreate(&parent, 0) != hipSuccess) return fail(hs[0], LB_EDEVICE, "hipGraphCreate");
+    for (size_t i = 0; i < hs.size(); ++i) {
+        hipGraph_t child;
+        if (lb_status s = chain_of(hs[i], ks[i], &child)) {
+            (void)hipGraphDestroy(parent);
+            return s;
+        }
+        hipGraphNode_t node;
+        if (hipGraphAddChildGraphNode(&node, parent, nullptr, 0, child) != hipSuccess) {
+            (void)hipGraphDestroy(parent);
+            return fail(hs[i], LB_EDEVICE, "hipGraphAddChildGraphNode");
+        }
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(parent);
+        return fail(hs[0], LB_EDEVICE, "hipGraphInstantiate");
+    }
+    if (g_batches.size() >= MAX_BATCH_EXECS) {
+        drop_batch(g_batches.front());
+        g_batches.erase(g_batches.begin());
+    }
+    g_batches.push_back(BatchExec{hs, ks, curs, pars, parent, exec});
+    *out = exec;
+    return LB_OK;
+}
+
+lb_status step_eager(lb_handle *h, int n)
+{
+    for (int j = 0; j < n; ++j) {
+        lb_status s = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
+        if (s) return s;
+    }
+    return LB_OK;
+}
+
+lb_status ensure_event(lb_handle *h)
+{
+    if (!h->sync_ev && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(h, LB_EDEVICE, "hipEventCreate");
+    return LB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1024,18 +1147,24 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     if (e == hipSuccess) e = hipMemcpyAsync(drb, rho_b, N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cumpre, 0, L.pendc - L.cumpre, h->stream);
+    // device step counter: t = 0, no step taken (the stream is synchronised
+    // below, before g0 goes out of scope)
+    StepGeom g0;
+    std::memset(&g0, 0, sizeof(g0));
+    g0.first = 1;
+    if (e == hipSuccess) e = hipMemcpyAsync(geo(h), &g0, sizeof(g0), hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) {
         std::string m = std::string("lb_create: ") + hipGetErrorString(e);
         delete h;
         return fail(nullptr, LB_EDEVICE, m);
     }
-    HeadPos H = heads(h, nullptr, nullptr, nullptr, nullptr);
     dim3 grid((unsigned)L.nbm);
+    hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, h->stream, h->P, geo(h));
     if (p->storage == LB_F64)
-        hipLaunchKernelGGL(k_init<double>, grid, dim3(TPB), 0, h->stream, h->P, H, dry, drb, du, u ? 1 : 0,
+        hipLaunchKernelGGL(k_init<double>, grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
                            as<double>(h, L.pops));
     else
-        hipLaunchKernelGGL(k_init<float>, grid, dim3(TPB), 0, h->stream, h->P, H, dry, drb, du, u ? 1 : 0,
+        hipLaunchKernelGGL(k_init<float>, grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
                            as<float>(h, L.pops));
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -1093,9 +1222,64 @@ lb_status lb_timing_read(lb_handle *h, double *step_ms, double *prep_ms, long *s
     return LB_OK;
 }
 
+lb_status lb_step_batch(lb_handle *const *hs, const int *nsteps, int n)
+{
+    if (!hs || !nsteps || n < 1) return fail(nullptr, LB_EINVAL, "lb_step_batch: null argument or n < 1");
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || nsteps[i] < 0) return fail(nullptr, LB_EINVAL, "lb_step_batch: bad handle or step count");
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return fail(hs[i], LB_EINVAL, "lb_step_batch: a handle appears twice");
+        if (hs[i]->unstable) return fail(hs[i], LB_ESTATE, "handle is unstable; only lb_moments and lb_destroy");
+        if (hs[i]->p.check_interval > 0)
+            return fail(hs[i], LB_EINVAL, "lb_step_batch: handles with check_interval > 0 step with lb_step");
+    }
+    // eager part: a handle's first step, then the odd remainder; the even
+    // part goes into the batch graph
+    std::vector<lb_handle *> gh;
+    std::vector<int> gk, tail(n, 0);
+    for (int i = 0; i < n; ++i) {
+        int k = nsteps[i];
+        if (k > 0 && hs[i]->first) {
+            if (lb_status s = step_eager(hs[i], 1)) return s;
+            --k;
+        }
+        tail[i] = k & 1;
+        if (k - tail[i] > 0) {
+            gh.push_back(hs[i]);
+            gk.push_back(k - tail[i]);
+        }
+    }
+    if (!gh.empty()) {
+        hipGraphExec_t exec;
+        if (lb_status s = batch_exec(gh, gk, &exec)) return s;
+        const hipStream_t s0 = gh[0]->stream;
+        for (lb_handle *h : gh) {
+            if (h->stream == s0) continue;
+            if (lb_status s = ensure_event(h)) return s;
+            if (hipEventRecord(h->sync_ev, h->stream) != hipSuccess || hipStreamWaitEvent(s0, h->sync_ev, 0) != hipSuccess)
+                return fail(h, LB_EDEVICE, "lb_step_batch: stream ordering");
+        }
+        if (hipGraphLaunch(exec, s0) != hipSuccess) return fail(gh[0], LB_EDEVICE, "hipGraphLaunch");
+        if (lb_status s = ensure_event(gh[0])) return s;
+        if (hipEventRecord(gh[0]->sync_ev, s0) != hipSuccess) return fail(gh[0], LB_EDEVICE, "hipEventRecord");
+        for (size_t i = 0; i < gh.size(); ++i) {
+            lb_handle *h = gh[i];
+            if (h->stream != s0 && hipStreamWaitEvent(h->stream, gh[0]->sync_ev, 0) != hipSuccess)
+                return fail(h, LB_EDEVICE, "lb_step_batch: stream ordering");
+            h->t += gk[i];
+            h->first = 0;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        if (tail[i])
+            if (lb_status s = step_eager(hs[i], 1)) return s;
+    return LB_OK;
+}
+
 lb_status lb_destroy(lb_handle *h)
 {
     if (!h) return LB_EINVAL;
+    purge_batches(h);
     delete h;
     return LB_OK;
 }

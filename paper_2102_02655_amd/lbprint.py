@@ -19,8 +19,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16dev": 2, "f16dev": 3}
 RHEOLOGY = {"newtonian": 0, "power_law": 1, "cross": 2}
 FACE = {"periodic": 0, "wall": 1, "pressure": 2}
 
-EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_moments", "lb_time", "lb_timing", "lb_timing_read",
-           "lb_destroy", "lb_strerror", "lb_last_error")
+EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_time", "lb_timing",
+           "lb_timing_read", "lb_destroy", "lb_strerror", "lb_last_error")
 
 _d2 = C.c_double * 2
 _d3 = C.c_double * 3
@@ -93,6 +93,7 @@ def lib():
         L.lb_footprint.argtypes = [C.POINTER(Params), C.POINTER(C.c_size_t)]
         L.lb_create.argtypes = [C.POINTER(Params), vp, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.lb_step.argtypes = [vp, C.c_int]
+        L.lb_step_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), C.c_int]
         L.lb_moments.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Conserved)]
         L.lb_time.argtypes = [vp]
         L.lb_time.restype = C.c_long
@@ -103,7 +104,8 @@ def lib():
         L.lb_strerror.restype = C.c_char_p
         L.lb_last_error.argtypes = [vp]
         L.lb_last_error.restype = C.c_char_p
-        for f in ("lb_footprint", "lb_create", "lb_step", "lb_moments", "lb_timing", "lb_timing_read", "lb_destroy"):
+        for f in ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_timing", "lb_timing_read",
+                  "lb_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -171,6 +173,19 @@ def footprint(cfg: dict) -> int:
     if rc != LB_OK:
         _raise(rc)
     return int(n.value)
+
+
+def step_batch(sims, nsteps) -> None:
+    """Advance every Sim in `sims` by the matching count in `nsteps` (an int
+    applies to all) in one batched call (one graph launch for the even part)."""
+    n = len(sims)
+    if isinstance(nsteps, int):
+        nsteps = [nsteps] * n
+    hs = (C.c_void_p * n)(*[s._h.value for s in sims])
+    ks = (C.c_int * n)(*[int(k) for k in nsteps])
+    rc = lib().lb_step_batch(hs, ks, n)
+    if rc != LB_OK:
+        _raise(rc, sims[0]._h)
 
 
 def _require_gpu():

@@ -102,3 +102,13 @@ def test_nozzle_geometry_validation(lib):
     bad = dict(cfg, nozzle=dict(cfg["nozzle"], v=(1.5, 0.0)))
     with pytest.raises(LB.LBError):
         LB.footprint(bad)
+
+
+def test_step_batch_rejects_bad_arguments_without_touching_the_gpu(lib):
+    vp = C.c_void_p
+    ks = (C.c_int * 1)(2)
+    assert lib.lb_step_batch(None, ks, 1) == LB.LB_EINVAL
+    hs = (vp * 1)(None)
+    assert lib.lb_step_batch(hs, ks, 1) == LB.LB_EINVAL
+    assert lib.lb_step_batch(hs, ks, 0) == LB.LB_EINVAL
+    assert b"lb_step_batch" in lib.lb_last_error(None)
