@@ -93,6 +93,51 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
           file=sys.stderr, flush=True)
 
 
+def serve(args):
+    """Serving sweep: the parameter-sweep trace through the continuous-batching
+    server, then through one-at-a-time plain stepping, on the same GPU."""
+    import numpy as np
+    import torch
+
+    from paper_2102_02655_amd import lbprint as LB
+    from paper_2102_02655_amd import serving as S
+
+    reqs = S.make_requests(count=args.serve_count, seed=4, rate=args.serve_rate, steps=args.serve_steps)
+    log = (lambda m: print(m, file=sys.stderr, flush=True)) if args.verbose else None
+    warm = S.make_requests(count=2, seed=99, rate=1000.0, lmin=32, lmax=40, steps=4)
+    S.Server(8 << 30, chunk=2).run(warm)  # library load, first captures
+    torch.cuda.synchronize()
+    batched = S.Server(int(args.serve_budget_gb * 1e9), chunk=args.serve_chunk, keep_fields=False).run(reqs, log=log)
+    seq = S.run_sequential(reqs, log=log)
+    # spot check: a few requests rerun alone reproduce the served masses bit for bit
+    same = True
+    by_id = {r.id: r for r in batched.results}
+    for req in reqs[:3]:
+        sim = LB.Sim(req.cfg, req.ry, req.rb)
+        sim.step(req.steps)
+        _, _, _, cons = sim.moments(dtype=np.float64)
+        same &= bool(np.array_equal(cons["mass"], by_id[req.id].mass))
+        sim.close()
+    b, q = batched.summary(), seq.summary()
+    out = {
+        "metric": "sweep sims/hour",
+        "value": b["sims_per_hour"],
+        "unit": "sims/hour",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"parameter sweep: {args.serve_count} printing simulations, cubic boxes L~U{{32..160}}, "
+                               f"{args.serve_steps} steps each, Poisson arrivals {args.serve_rate}/s",
+                   "budget_GB": args.serve_budget_gb, "chunk": args.serve_chunk},
+        "batched": b,
+        "sequential": q,
+        "mix_equals_alone": same,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,10 +146,21 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", action="store_true", help="first run a plain copy of known size (PMC scaling)")
+    ap.add_argument("--serve", action="store_true", help="run the serving sweep instead of the step benchmark")
+    ap.add_argument("--serve-count", type=int, default=256)
+    ap.add_argument("--serve-steps", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-chunk", type=int, default=20)
+    ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        serve(args)
+        return
 
     import torch
 

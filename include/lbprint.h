@@ -133,18 +133,17 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
 lb_status lb_step(lb_handle *h, int nsteps);
 
 /* Batched stepping: advance handle hs[i] by nsteps[i] steps, i = 0 .. n-1
- * (distinct handles on one device; any mix of sizes, storage forms and
- * parameters; check_interval must be 0).  A handle's first step and an odd
- * remainder run as ordinary launches on its own stream; the even part of
- * every handle runs in ONE graph launch on hs[0]'s stream, each handle's
- * steps a captured chain of kernels (an independent branch of the graph, so
- * the handles' work overlaps on the device).  Chains and instantiated batch
- * graphs are cached and replayed while the same handles are stepped by the
- * same counts; a handle's cached graphs are released by lb_destroy.  Work is
- * ordered after earlier work on every handle's stream and before later work
- * on it (events).  The result of every handle is bit-identical to stepping
- * it alone with lb_step.  Asynchronous; LB_EINVAL on bad arguments,
- * LB_ESTATE on an unstable handle, LB_EDEVICE if a graph call fails. */
+ * (distinct handles; any mix of sizes, storage forms and parameters;
+ * check_interval must be 0).  A handle's first step and an odd remainder run
+ * as ordinary launches; the even part is ONE launch of a HIP graph holding
+ * that many steps of the handle (captured once on a private stream,
+ * instantiated, and cached in the handle -- at most four chains, keyed by
+ * the step count and the step parity -- then replayed on every later call
+ * with the same count).  Everything is enqueued on each handle's own stream,
+ * so handles on different streams run concurrently.  The result of every
+ * handle is bit-identical to stepping it alone with lb_step.  Asynchronous;
+ * LB_EINVAL on bad arguments, LB_ESTATE on an unstable handle, LB_EDEVICE if
+ * a graph call fails.  The cached graphs are released by lb_destroy. */
 lb_status lb_step_batch(lb_handle *const *hs, const int *nsteps, int n);
 
 /* Fields and conserved sums at the current step.  rho_y, rho_b (N values) and
@@ -171,7 +170,8 @@ long lb_time(const lb_handle *h);
 lb_status lb_timing(lb_handle *h, int enable);
 lb_status lb_timing_read(lb_handle *h, double *step_ms, double *prep_ms, long *steps);
 
-/* Release the handle (host memory only; the workspace stays the caller's). */
+/* Release the handle (host memory and its cached graphs; waits for the
+ * handle's stream if graphs were cached; the workspace stays the caller's). */
 lb_status lb_destroy(lb_handle *h);
 
 const char *lb_strerror(lb_status s);

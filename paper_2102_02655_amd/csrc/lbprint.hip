@@ -713,22 +713,20 @@ struct lb_handle {
     size_t nev = 0;
     double acc_step = 0.0, acc_prep = 0.0;
     long acc_n = 0;
-    // batched stepping (lb_step_batch): captured k-step chains, keyed by
-    // (k, population buffer, step parity), a private capture stream and an
-    // event for cross-stream ordering
+    // batched stepping (lb_step_batch): instantiated k-step chains of this
+    // handle, keyed by (k, population buffer, step parity), captured on a
+    // private stream
     struct Chain {
         int k, cur, parity;
-        hipGraph_t g;
+        hipGraphExec_t exec;
     };
     std::vector<Chain> chains;
     hipStream_t cap = nullptr;
-    hipEvent_t sync_ev = nullptr;
     ~lb_handle()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-        for (Chain &c : chains) (void)hipGraphDestroy(c.g);
+        for (Chain &c : chains) (void)hipGraphExecDestroy(c.exec);
         if (cap) (void)hipStreamDestroy(cap);
-        if (sync_ev) (void)hipEventDestroy(sync_ev);
     }
 };
 
@@ -974,15 +972,19 @@ lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, i
 
 // ---------------------------------------------------------------- batching
 
-// k steps of one handle captured as a graph (k even: the buffers a step uses
-// depend on the step's parity only, so the chain replays correctly for as
-// long as the handle's parity and population buffer match the key).
-lb_status chain_of(lb_handle *h, int k, hipGraph_t *out)
+constexpr size_t MAX_CHAINS = 4;
+
+// The instantiated graph of k steps of one handle (k even: the buffers a
+// step uses depend on the step's parity only, so the chain replays correctly
+// while the handle's parity and population buffer match the key).  Captured
+// on the handle's private stream; the host-side state is restored afterwards
+// (capturing runs nothing).
+lb_status chain_exec(lb_handle *h, int k, hipGraphExec_t *out)
 {
     const int parity = (int)(h->t & 1);
     for (const lb_handle::Chain &c : h->chains)
         if (c.k == k && c.cur == h->cur && c.parity == parity) {
-            *out = c.g;
+            *out = c.exec;
             return LB_OK;
         }
     if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
@@ -990,9 +992,9 @@ lb_status chain_of(lb_handle *h, int k, hipGraph_t *out)
     const hipStream_t saved = h->stream;
     const int cur = h->cur, first = h->first, timing = h->timing;
     const long t = h->t;
-    h->timing = 0;
     if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(h, LB_EDEVICE, "hipStreamBeginCapture");
+    h->timing = 0;
     h->stream = h->cap;
     lb_status st = LB_OK;
     for (int j = 0; j < k && st == LB_OK; ++j)
@@ -1004,86 +1006,22 @@ lb_status chain_of(lb_handle *h, int k, hipGraph_t *out)
     h->first = first;
     h->t = t;
     h->timing = timing;
-    if (st != LB_OK) {
+    if (st != LB_OK || e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
-        return st;
-    }
-    if (e != hipSuccess || !g) return fail(h, LB_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
-    h->chains.push_back(lb_handle::Chain{k, cur, (int)(t & 1), g});
-    *out = g;
-    return LB_OK;
-}
-
-// Instantiated batch graphs: one child node per handle, no dependencies
-// between them, so the handles' chains run concurrently.
-struct BatchExec {
-    std::vector<lb_handle *> hs;
-    std::vector<int> ks, curs, parities;
-    hipGraph_t parent;
-    hipGraphExec_t exec;
-};
-std::mutex g_batch_mu;
-std::vector<BatchExec> g_batches;
-constexpr size_t MAX_BATCH_EXECS = 16;
-
-void drop_batch(BatchExec &b)
-{
-    (void)hipGraphExecDestroy(b.exec);
-    (void)hipGraphDestroy(b.parent);
-}
-
-void purge_batches(lb_handle *h)
-{
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    for (size_t i = 0; i < g_batches.size();) {
-        bool has = false;
-        for (lb_handle *x : g_batches[i].hs) has |= x == h;
-        if (has) {
-            drop_batch(g_batches[i]);
-            g_batches.erase(g_batches.begin() + (long)i);
-        } else {
-            ++i;
-        }
-    }
-}
-
-lb_status batch_exec(const std::vector<lb_handle *> &hs, const std::vector<int> &ks, hipGraphExec_t *out)
-{
-    std::vector<int> curs, pars;
-    for (lb_handle *h : hs) {
-        curs.push_back(h->cur);
-        pars.push_back((int)(h->t & 1));
-    }
-    std::lock_guard<std::mutex> lk(g_batch_mu);
-    for (BatchExec &b : g_batches)
-        if (b.hs == hs && b.ks == ks && b.curs == curs && b.parities == pars) {
-            *out = b.exec;
-            return LB_OK;
-        }
-    hipGraph_t parent = nullptr;
-    if (hipGraphCreate(&parent, 0) != hipSuccess) return fail(hs[0], LB_EDEVICE, "hipGraphCreate");
-    for (size_t i = 0; i < hs.size(); ++i) {
-        hipGraph_t child;
-        if (lb_status s = chain_of(hs[i], ks[i], &child)) {
-            (void)hipGraphDestroy(parent);
-            return s;
-        }
-        hipGraphNode_t node;
-        if (hipGraphAddChildGraphNode(&node, parent, nullptr, 0, child) != hipSuccess) {
-            (void)hipGraphDestroy(parent);
-            return fail(hs[i], LB_EDEVICE, "hipGraphAddChildGraphNode");
-        }
+        if (st != LB_OK) return st;
+        return fail(h, LB_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
     }
     hipGraphExec_t exec = nullptr;
-    if (hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(parent);
-        return fail(hs[0], LB_EDEVICE, "hipGraphInstantiate");
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(h, LB_EDEVICE, "hipGraphInstantiate");
+    if (h->chains.size() >= MAX_CHAINS) {
+        // an evicted chain may still be running on the handle's stream
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(h, LB_EDEVICE, "hipStreamSynchronize");
+        (void)hipGraphExecDestroy(h->chains.front().exec);
+        h->chains.erase(h->chains.begin());
     }
-    if (g_batches.size() >= MAX_BATCH_EXECS) {
-        drop_batch(g_batches.front());
-        g_batches.erase(g_batches.begin());
-    }
-    g_batches.push_back(BatchExec{hs, ks, curs, pars, parent, exec});
+    h->chains.push_back(lb_handle::Chain{k, cur, parity, exec});
     *out = exec;
     return LB_OK;
 }
@@ -1094,13 +1032,6 @@ lb_status step_eager(lb_handle *h, int n)
         lb_status s = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
         if (s) return s;
     }
-    return LB_OK;
-}
-
-lb_status ensure_event(lb_handle *h)
-{
-    if (!h->sync_ev && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess)
-        return fail(h, LB_EDEVICE, "hipEventCreate");
     return LB_OK;
 }
 
@@ -1233,53 +1164,34 @@ lb_status lb_step_batch(lb_handle *const *hs, const int *nsteps, int n)
         if (hs[i]->p.check_interval > 0)
             return fail(hs[i], LB_EINVAL, "lb_step_batch: handles with check_interval > 0 step with lb_step");
     }
-    // eager part: a handle's first step, then the odd remainder; the even
-    // part goes into the batch graph
-    std::vector<lb_handle *> gh;
-    std::vector<int> gk, tail(n, 0);
+    // per handle: its first step and an odd remainder as ordinary launches,
+    // the even part as one launch of its instantiated chain
     for (int i = 0; i < n; ++i) {
+        lb_handle *h = hs[i];
         int k = nsteps[i];
-        if (k > 0 && hs[i]->first) {
-            if (lb_status s = step_eager(hs[i], 1)) return s;
+        if (k > 0 && h->first) {
+            if (lb_status s = step_eager(h, 1)) return s;
             --k;
         }
-        tail[i] = k & 1;
-        if (k - tail[i] > 0) {
-            gh.push_back(hs[i]);
-            gk.push_back(k - tail[i]);
-        }
-    }
-    if (!gh.empty()) {
-        hipGraphExec_t exec;
-        if (lb_status s = batch_exec(gh, gk, &exec)) return s;
-        const hipStream_t s0 = gh[0]->stream;
-        for (lb_handle *h : gh) {
-            if (h->stream == s0) continue;
-            if (lb_status s = ensure_event(h)) return s;
-            if (hipEventRecord(h->sync_ev, h->stream) != hipSuccess || hipStreamWaitEvent(s0, h->sync_ev, 0) != hipSuccess)
-                return fail(h, LB_EDEVICE, "lb_step_batch: stream ordering");
-        }
-        if (hipGraphLaunch(exec, s0) != hipSuccess) return fail(gh[0], LB_EDEVICE, "hipGraphLaunch");
-        if (lb_status s = ensure_event(gh[0])) return s;
-        if (hipEventRecord(gh[0]->sync_ev, s0) != hipSuccess) return fail(gh[0], LB_EDEVICE, "hipEventRecord");
-        for (size_t i = 0; i < gh.size(); ++i) {
-            lb_handle *h = gh[i];
-            if (h->stream != s0 && hipStreamWaitEvent(h->stream, gh[0]->sync_ev, 0) != hipSuccess)
-                return fail(h, LB_EDEVICE, "lb_step_batch: stream ordering");
-            h->t += gk[i];
+        const int g = k & ~1;
+        if (g > 0) {
+            hipGraphExec_t exec;
+            if (lb_status s = chain_exec(h, g, &exec)) return s;
+            if (hipGraphLaunch(exec, h->stream) != hipSuccess) return fail(h, LB_EDEVICE, "hipGraphLaunch");
+            h->t += g;
             h->first = 0;
         }
+        if (k & 1)
+            if (lb_status s = step_eager(h, 1)) return s;
     }
-    for (int i = 0; i < n; ++i)
-        if (tail[i])
-            if (lb_status s = step_eager(hs[i], 1)) return s;
     return LB_OK;
 }
 
 lb_status lb_destroy(lb_handle *h)
 {
     if (!h) return LB_EINVAL;
-    purge_batches(h);
+    // the handle's chains may still run on its stream
+    if (!h->chains.empty()) (void)hipStreamSynchronize(h->stream);
     delete h;
     return LB_OK;
 }
