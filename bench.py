@@ -26,8 +26,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per lattice update: each of the 2 x 19 populations read
-# once and written once.
-BYTES_PER_LU = {"f64": 608, "f32": 304}
+# once and written once; the reduced forms also read and write the cell's
+# five FP32 moments (2 x (38 x 2 + 5 x 4) B).
+BYTES_PER_LU = {"f64": 608, "f32": 304, "bf16dev": 192, "f16dev": 192}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_print_bed_512x256x128_f32_traffic.md")
 
 
@@ -143,7 +144,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16dev", "f16dev"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", action="store_true", help="first run a plain copy of known size (PMC scaling)")
     ap.add_argument("--serve", action="store_true", help="run the serving sweep instead of the step benchmark")
@@ -200,7 +201,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.storage,
+        "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"print-bed filament, D3Q19 {nx}x{ny}x{nz}, moving head u=0.01, power-law n=0.5",
                    "cells": cells, "storage": args.storage},

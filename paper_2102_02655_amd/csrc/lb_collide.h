@@ -105,6 +105,54 @@ __device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &
     }(std::make_integer_sequence<int, lbq::Q>{});
 }
 
+// Reduced storage: link I's deviation from the equilibrium of this cell's
+// post-collision moments (rho_Y, rho_B, u'), 16-bit (the deviation is the
+// non-equilibrium, perturbation and recolouring part of the compact form).
+template <int ST, int I>
+__device__ __forceinline__ void store_one_dev(const DevParams &P, const OutCoef<float> &K, float rY, float rB,
+                                              float vx, float vy, float vz, gchar *pw, unsigned cellb)
+{
+    typedef __attribute__((address_space(1))) unsigned gU;
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+    float Tst, cgw = 0.f;
+    if constexpr (I == 0) {
+        Tst = K.t0;
+    } else {
+        float q = K.k1;
+        if (X) q += X > 0 ? K.ax : -K.ax;
+        if (Yc) q += Yc > 0 ? K.ay : -K.ay;
+        if (Z) q += Z > 0 ? K.az : -K.az;
+        if (X) q += K.bxx;
+        if (Yc) q += K.byy;
+        if (Z) q += K.bzz;
+        if (X && Yc) q += X * Yc > 0 ? K.bxy : -K.bxy;
+        if (X && Z) q += X * Z > 0 ? K.bxz : -K.bxz;
+        if (Yc && Z) q += Yc * Z > 0 ? K.byz : -K.byz;
+        const float wi = float(lbq::w(I));
+        Tst = wi * q;
+        float cg = 0.f;
+        if (X) cg += X > 0 ? K.rx : -K.rx;
+        if (Yc) cg += Yc > 0 ? K.ry : -K.ry;
+        if (Z) cg += Z > 0 ? K.rz : -K.rz;
+        cgw = wi * float(lbq::inv_len(I)) * cg;
+    }
+    const float Yst = float(__builtin_fma(K.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
+    float fT, fY;
+    feq_TY<I>(P, rY, rB, vx, vy, vz, fT, fY);
+    const unsigned wd = (unsigned)encode_dev<ST, I>(Tst - fT) | ((unsigned)encode_dev<ST, I>(Yst - fY) << 16);
+    __builtin_nontemporal_store(wd, reinterpret_cast<gU *>(pw + cellb));
+}
+
+template <int ST>
+__device__ __forceinline__ void store_all_dev(const DevParams &P, const OutCoef<float> &K, float rY, float rB,
+                                              float vx, float vy, float vz, gchar *base, unsigned long long pstride,
+                                              unsigned cellb)
+{
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        ((store_one_dev<ST, I>(P, K, rY, rB, vx, vy, vz, base + (unsigned long long)I * pstride, cellb)), ...);
+    }(std::make_integer_sequence<int, lbq::Q>{});
+}
+
 // What the collision needs of a cell, derived from its moment set: the two
 // masses (FP64), momentum, the total non-equilibrium stress and the BGK
 // factor 1 - 1/tau of the local mixture relaxation time.
@@ -161,10 +209,11 @@ __device__ __forceinline__ CellState<R> cell_state(const DevParams &P, const Mom
 // Collide one fluid cell from its state and colour gradients; store the 38
 // post-collision values at the cell (the next step pulls them) and return
 // rho_Y, rho_B and the bare velocity for the boundary rules of the next pull.
-template <typename R>
+template <typename R, int ST = ST_PLAIN>
 __device__ __forceinline__ void collide_state(const DevParams &P, const CellState<R> &C, const Grad<R> &G, int z,
                                               char *__restrict__ dst, unsigned long long pstride, unsigned cellb,
-                                              R &out_rY, R &out_rB, R (&out_u)[3])
+                                              R &out_rY, R &out_rB, R (&out_u)[3], float *__restrict__ mo_dst = nullptr,
+                                              long long cell = 0)
 {
     const double rho_d = P.rho_ref + C.drho;
     const double fracY_d = C.rY / rho_d;
@@ -231,7 +280,17 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
     K.ry = rec * G.g[1];
     K.rz = rec * G.g[2];
     K.fracY = fracY_d;
-    store_all<R>(P, K, fresh_global(dst), fresh_uniform(pstride), cellb);
+    if constexpr (ST == ST_PLAIN) {
+        store_all<R>(P, K, fresh_global(dst), fresh_uniform(pstride), cellb);
+    } else {
+        store_all_dev<ST>(P, K, rY, rB, vx, vy, vz, fresh_global(dst), fresh_uniform(pstride), cellb);
+        const long long N = P.N;
+        mo_dst[cell] = rY;
+        mo_dst[N + cell] = rB;
+        mo_dst[2 * N + cell] = vx;
+        mo_dst[3 * N + cell] = vy;
+        mo_dst[4 * N + cell] = vz;
+    }
     out_rY = rY;
     out_rB = rB;
     out_u[0] = ux;

@@ -195,24 +195,117 @@ struct Flux {
     double wallY, wallB, openY, openB;
 };
 
+// ------------------------------------------------------ population storage
+// ST 0: populations stored in the arithmetic type R (set T: f - w rho_ref,
+// set Y: f^Y).  ST 1 / 2 (reduced storage, R = float): the deviation of each
+// post-collision population from the equilibrium of its source cell's
+// moments (rho_Y, rho_B, u'), as BF16 (ST 1) or as FP16 of delta / w_i
+// (ST 2), with the moments stored in FP32 beside them.  The two deviations
+// of link i (set T in the low half, set Y in the high half) share one 32-bit
+// word: 19 planes of words, one memory instruction per link.  Encoder and decoder
+// evaluate the equilibrium with the same function (no contraction), so the
+// only loss is the 16-bit rounding of the deviation.
+enum { ST_PLAIN = 0, ST_BF16 = 1, ST_F16 = 2 };
+constexpr int NMO = 5;  // stored source moments: rho_Y, rho_B, u'_x, u'_y, u'_z
+
+__device__ __forceinline__ unsigned short enc_bf16(float v)
+{
+    unsigned u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float dec_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ __forceinline__ unsigned short enc_f16(float v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
+__device__ __forceinline__ float dec_f16(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+template <int ST, int I>
+__device__ __forceinline__ unsigned short encode_dev(float d)
+{
+    if constexpr (ST == ST_BF16)
+        return enc_bf16(d);
+    else
+        return enc_f16(d * float(1.0 / lbq::w(I)));
+}
+
+template <int ST, int I>
+__device__ __forceinline__ float decode_dev(unsigned short h)
+{
+    if constexpr (ST == ST_BF16)
+        return dec_bf16(h);
+    else
+        return dec_f16(h) * float(lbq::w(I));
+}
+
+// Equilibrium of link I for moments (rho_Y, rho_B, u), in the stored bases:
+// T = f^eq - w_I rho_ref (both colours), Y = f^{Y,eq}.
+template <int I>
+__device__ __forceinline__ void feq_TY(const DevParams &P, float rY, float rB, float ux, float uy, float uz,
+                                       float &fT, float &fY)
+{
+#pragma clang fp contract(off)
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I), S = lbq::shell(I);
+    const float w = float(lbq::w(I));
+    float cu = 0.f;
+    if (X) cu = X > 0 ? ux : -ux;
+    if (Yc) cu = cu + (Yc > 0 ? uy : -uy);
+    if (Z) cu = cu + (Z > 0 ? uz : -uz);
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float E = w * (3.f * cu + 4.5f * (cu * cu) - 1.5f * uu);
+    const float rho = rY + rB;
+    fY = rY * (float(P.phi[0][S]) + E);
+    fT = rY * float(P.phid[0][S]) + rB * float(P.phid[1][S]) + (rho - float(P.rho_ref)) * w + rho * E;
+}
+
+// Read access to the post-collision populations of step t-1: the reduced
+// storage forms (R = float) in the primary template, plain storage below.
+template <typename R, int ST>
+struct PopSrc {
+    static_assert(sizeof(R) == 4, "reduced storage computes in FP32");
+    const unsigned *s;
+    const float *mo;  // NMO x N source moments
+    long long N;
+    template <int I>
+    __device__ __forceinline__ void get(const DevParams &P, long long cell, float &T, float &Y) const
+    {
+        const unsigned wd = s[I * N + cell];
+        const unsigned short dT = (unsigned short)(wd & 0xFFFFu), dY = (unsigned short)(wd >> 16);
+        float fT, fY;
+        feq_TY<I>(P, mo[cell], mo[N + cell], mo[2 * N + cell], mo[3 * N + cell], mo[4 * N + cell], fT, fY);
+        T = fT + decode_dev<ST, I>(dT);
+        Y = fY + decode_dev<ST, I>(dY);
+    }
+};
+
+template <typename R>
+struct PopSrc<R, ST_PLAIN> {
+    const R *s;
+    long long N;
+    template <int I>
+    __device__ __forceinline__ void get(const DevParams &, long long cell, R &T, R &Y) const
+    {
+        T = s[I * N + cell];
+        Y = s[(lbq::Q + I) * N + cell];
+    }
+};
+
 // Pull of one population pair (Eq. (lbm) as a pull): f_i(x, t) comes from
 // x - c_i at t-1, or, when that site is not fluid at t-1, from the boundary
 // rule applied to x's own post-collision population of the opposite link
 // (Sec. II.B: halfway bounce-back, Eq. (movwall) with the wall density
 // extrapolated inward, Eq. (movnozzle) on the lid, anti-bounce-back on
 // pressure faces).
-template <typename R, int I, bool FULL = true>
-__device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
+template <typename R, int I, bool FULL = true, typename PS>
+__device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, const PS &src,
                                          const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
                                          bool first, Mom<R> &M, Flux &fl)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
     constexpr int IB = lbq::opp(I);
     const long long N = P.N;
-    const R *sT = src;
-    const R *sY = src + (long long)lbq::Q * N;
     if (first) {
-        mom_add<R, I, FULL>(M, sT[I * N + cell], sY[I * N + cell]);
+        R T0, Y0;
+        src.template get<I>(P, cell, T0, Y0);
+        mom_add<R, I, FULL>(M, T0, Y0);
         return;
     }
     int xs = X ? wrap(x - X, P.nx) : x;
@@ -221,12 +314,14 @@ __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, c
     int st = (Z == 0 && !near) ? ST_FLUID : classify(P, H.hx_p, H.hy_p, xs, ys, zs, near);
     if (st == ST_FLUID) {
         long long sc = ((long long)zs * P.ny + ys) * P.nx + xs;
-        mom_add<R, I, FULL>(M, sT[I * N + sc], sY[I * N + sc]);
+        R T0, Y0;
+        src.template get<I>(P, sc, T0, Y0);
+        mom_add<R, I, FULL>(M, T0, Y0);
         return;
     }
     // the link from x towards the wall is IB; its post-collision values
-    const R Tout = sT[IB * N + cell];
-    const R Yout = sY[IB * N + cell];
+    R Tout, Yout;
+    src.template get<IB>(P, cell, Tout, Yout);
     const R wi = R(lbq::w(I));
     R T, Yv;
     if (st == ST_OPEN_LO || st == ST_OPEN_HI) {
@@ -316,8 +411,8 @@ __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, c
     mom_add<R, I, FULL>(M, T, Yv);
 }
 
-template <typename R, bool FULL = true, int I = 0>
-__device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
+template <typename R, bool FULL = true, int I = 0, typename PS>
+__device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, const PS &src,
                                          const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
                                          bool first, Mom<R> &M, Flux &fl)
 {
@@ -409,6 +504,21 @@ __device__ __forceinline__ void pull_bulk_issue(gcchar *base, unsigned long long
         vY[I] = *reinterpret_cast<gR *>(pY + off);
         pT += pstride;
         pY += pstride;
+    }
+}
+
+// The 19 word loads of a bulk pull in the reduced storage forms.
+template <bool FIRST>
+__device__ __forceinline__ void pull_bulk_issue_words(gcchar *base, unsigned long long pstride, const BulkIdx &B,
+                                                      unsigned cellb, unsigned (&v)[lbq::Q])
+{
+    typedef __attribute__((address_space(1))) const unsigned gU;
+    gcchar *p = base;
+#pragma unroll
+    for (int I = 0; I < lbq::Q; ++I) {
+        const unsigned off = FIRST ? cellb : B.zo[1 - lbq::cz(I)] + B.yo[1 - lbq::cy(I)] + B.xo[1 - lbq::cx(I)];
+        v[I] = *reinterpret_cast<gU *>(p + off);
+        p += pstride;
     }
 }
 

@@ -368,18 +368,26 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, const S
 // relaxation time included.  One barrier per
 // plane.  Loads and stores are issued by different waves, so neither waits
 // behind the other in a wave's queue of outstanding memory operations.
-template <typename R, int TY, bool FIRST>
+template <typename R, int TY, bool FIRST, int ST = ST_PLAIN>
 __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, const StepGeom *__restrict__ G,
-                                                                  FusedGrid FG, const R *__restrict__ src,
-                                                                  R *__restrict__ dst,
+                                                                  FusedGrid FG, const void *__restrict__ src,
+                                                                  void *__restrict__ dst,
                                                                   const double *__restrict__ momd,
                                                                   const R *__restrict__ mom,
                                                                   const R *__restrict__ chi,
                                                                   const R *__restrict__ ghost,
-                                                                  R *__restrict__ mac_next)
+                                                                  R *__restrict__ mac_next,
+                                                                  const float *__restrict__ mo_src,
+                                                                  float *__restrict__ mo_dst)
 {
+    // E: stored element type; reduced storage keeps 16-bit deviations and
+    // decodes them with the source cells' moments (an LDS ring of planes, the
+    // tile with a two-cell halo: the ring cells' sources included)
+    typedef typename std::conditional<ST == ST_PLAIN, R, unsigned>::type E;
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
+    constexpr int MW = 68, MH = TY + 4, MR = MW * MH;  // moment region: x0-2 .. x0+65, y0-2 .. y0+TY+1
     constexpr bool DEEP = sizeof(R) == 4;
+    __shared__ float mring[ST == ST_PLAIN ? 1 : 4][NMO][ST == ST_PLAIN ? 1 : MR];
     const HeadPos H = G->H;
     const Box3 head = G->bx[0];
     __shared__ R chi_l[4][3][PL];
@@ -396,7 +404,7 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long N = P.N;
     const long long plane_sz = (long long)P.nx * P.ny;
-    const unsigned long long pstride = (unsigned long long)N * sizeof(R);
+    const unsigned long long pstride = (unsigned long long)N * sizeof(E);
 
     if (wave >= TY + 3) {
         // ---------------- collider: tile row wave - TY - 3
@@ -407,6 +415,9 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
         const int row = r + 1, col = lane + 1;
         const int ii = r * 64 + lane;
         const long long col_off = (long long)yw * P.nx + xw;
+        // every wave of the block passes the same barriers: one after the
+        // loaders' prologue, then one per plane
+        __syncthreads();
         for (int p = z0 - 1; p <= z1 + 1; ++p) {
             const int c = p - 2;
             if (tile && c >= z0 && st_ok[c & 3][ii]) {
@@ -438,8 +449,8 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
                 const CellState<R> C = cell_state<R>(P, M);
                 const long long ccell = col_off + (long long)c * plane_sz;
                 R rY, rB, u[3];
-                collide_state<R>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,
-                                 (unsigned)(ccell * (long long)sizeof(R)), rY, rB, u);
+                collide_state<R, ST>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,
+                                     (unsigned)(ccell * (long long)sizeof(E)), rY, rB, u, mo_dst, ccell);
                 if (macro_needed(P, H, xw, yw, c)) {
                     mac_next[ccell] = rY;
                     mac_next[N + ccell] = rB;
@@ -522,13 +533,69 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
         J.cell = J.ghost ? 0 : col_off + (long long)J.zp * plane_sz;
         return J;
     };
-    auto issue = [&](int p, R(&vT)[lbq::Q], R(&vY)[lbq::Q]) {
+    auto issue = [&](int p, E(&vT)[lbq::Q], E(&vY)[lbq::Q]) {
         const PlaneJob J = job(p);
-        if (J.bulk)
-            pull_bulk_issue<R, FIRST>(fresh_global_c(src), fresh_uniform(pstride), bulk_index<R>(P, xw, yw, J.zp),
-                                      (unsigned)(J.cell * (long long)sizeof(R)), vT, vY);
+        if (J.bulk) {
+            if constexpr (ST == ST_PLAIN)
+                pull_bulk_issue<E, FIRST>(fresh_global_c(reinterpret_cast<const E *>(src)), fresh_uniform(pstride),
+                                          bulk_index<E>(P, xw, yw, J.zp), (unsigned)(J.cell * (long long)sizeof(E)),
+                                          vT, vY);
+            else
+                pull_bulk_issue_words<FIRST>(fresh_global_c(reinterpret_cast<const E *>(src)), fresh_uniform(pstride),
+                                             bulk_index<E>(P, xw, yw, J.zp), (unsigned)(J.cell * (long long)sizeof(E)),
+                                             vT);
+        }
     };
-    auto reduce = [&](int p, const R(&vT)[lbq::Q], const R(&vY)[lbq::Q]) {
+
+    // moment ring (reduced storage): this thread's share of the region, two
+    // cells at most, loaded one iteration before they are written to LDS
+    const int lx = cx - x0, ly = cy - y0;  // tile-relative position (ring: -1 / 64, -1 / TY)
+    float mreg[2][NMO];
+    auto m_issue = [&](int q) {
+        if constexpr (ST != ST_PLAIN) {
+            int zq = q;
+            const bool ok = P.periodic_z || (q >= 0 && q < P.nz);
+            if (P.periodic_z) zq = wrap_any(q, P.nz);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int k = threadIdx.x + r * (TY + 3) * 64;
+                if (ok && k < MR) {
+                    const int mx = wrap_any(x0 - 2 + k % MW, P.nx), my = wrap_any(y0 - 2 + k / MW, P.ny);
+                    const long long mc = (long long)zq * plane_sz + (long long)my * P.nx + mx;
+#pragma unroll
+                    for (int m = 0; m < NMO; ++m) mreg[r][m] = mo_src[m * N + mc];
+                }
+            }
+        }
+    };
+    auto m_write = [&](int q) {
+        if constexpr (ST != ST_PLAIN) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int k = threadIdx.x + r * (TY + 3) * 64;
+                if (k < MR)
+#pragma unroll
+                    for (int m = 0; m < NMO; ++m) mring[q & 3][m][k] = mreg[r][m];
+            }
+        }
+    };
+    // decode of link I of the pulled cell at plane p (reduced storage)
+    auto decode = [&]<int I>(int p, E vT, E vY, R &T, R &Y) {
+        if constexpr (ST == ST_PLAIN) {
+            T = vT;
+            Y = vY;
+        } else {
+            constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+            const int sl = FIRST ? (p & 3) : ((p - Z) & 3);
+            const int k = FIRST ? (ly + 2) * MW + lx + 2 : (ly + 2 - Yc) * MW + lx + 2 - X;
+            float fT, fY;
+            feq_TY<I>(P, mring[sl][0][k], mring[sl][1][k], mring[sl][2][k], mring[sl][3][k], mring[sl][4][k], fT, fY);
+            T = fT + decode_dev<ST, I>((unsigned short)(vT & 0xFFFFu));
+            Y = fY + decode_dev<ST, I>((unsigned short)(vT >> 16));
+        }
+    };
+
+    auto reduce = [&](int p, const E(&vT)[lbq::Q], const E(&vY)[lbq::Q]) {
         const PlaneJob J = job(p);
         if (!J.load) return;
         R cN, cY, cB;
@@ -557,7 +624,20 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
             } else {
                 // one code path for tile and ring cells (a branch here lets
                 // the compiler hoist all 38 FP64 conversions above it)
-                mom_add_all<R, true>(M, vT, vY);
+                if constexpr (ST == ST_PLAIN) {
+                    mom_add_all<R, true>(M, vT, vY);
+                } else {
+                    [&]<int... I>(std::integer_sequence<int, I...>) {
+                        (
+                            [&] {
+                                R T, Y;
+                                decode.template operator()<I>(p, vT[I], vY[I], T, Y);
+                                mom_add<R, I, true>(M, T, Y);
+                                __builtin_amdgcn_sched_barrier(0);
+                            }(),
+                            ...);
+                    }(std::make_integer_sequence<int, lbq::Q>{});
+                }
                 chi_of<R>(P, R(M.dm[1]), R(P.rho_ref + M.dm[0] - M.dm[1]), cN, cY, cB);
             }
             if (J.own && fluid) {
@@ -576,8 +656,9 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
         if (wave < TY) st_ok[p & 3][ii] = cur_ok ? 1 : 0;
     };
 
-    R aT[lbq::Q], aY[lbq::Q];
+    E aT[lbq::Q], aY[lbq::Q];
     if constexpr (!DEEP) {
+        __syncthreads();
         for (int p = z0 - 1; p <= z1 + 1; ++p) {
             issue(p, aT, aY);
             __builtin_amdgcn_sched_barrier(0);
@@ -586,14 +667,27 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
         }
         return;
     }
-    R bT[lbq::Q], bY[lbq::Q];
+    E bT[lbq::Q], bY[lbq::Q];
+    if constexpr (ST != ST_PLAIN) {
+        // moments of planes z0 - 2 .. z0 in LDS, z0 + 1 in registers
+        for (int q = z0 - 2; q <= z0; ++q) {
+            m_issue(q);
+            m_write(q);
+        }
+        m_issue(z0 + 1);
+    }
     issue(z0 - 1, aT, aY);
+    __syncthreads();
     for (int p = z0 - 1; p <= z1 + 1; p += 2) {
+        m_write(p + 2);
+        m_issue(p + 3);
         issue(p + 1, bT, bY);
         __builtin_amdgcn_sched_barrier(0);
         reduce(p, aT, aY);
         __syncthreads();
         if (p + 1 > z1 + 1) break;
+        m_write(p + 3);
+        m_issue(p + 4);
         issue(p + 2, aT, aY);
         __builtin_amdgcn_sched_barrier(0);
         reduce(p + 1, bT, bY);

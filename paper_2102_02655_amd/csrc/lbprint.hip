@@ -99,20 +99,30 @@ __device__ __forceinline__ void dens(const DevParams &P, const double *__restric
 // ------------------------------------------------------------------ kernels
 
 // Initial state: f^k = f^{k,eq}(rho^k, u) at the fluid cells of step 0.
-template <typename R>
+// Reduced storage: zero deviations and the cell's moments (the decoded
+// populations are then the equilibrium).
+template <typename R, int ST>
 __global__ __launch_bounds__(TPB) void k_init(DevParams P, const StepGeom *__restrict__ G,
                                               const double *__restrict__ rho_y, const double *__restrict__ rho_b,
-                                              const double *__restrict__ u, int has_u, R *__restrict__ dst)
+                                              const double *__restrict__ u, int has_u, void *__restrict__ dst_v,
+                                              float *__restrict__ mo)
 {
     const HeadPos H = G->H;
     long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     if (cell >= P.N) return;
     int x, y, z;
     cell_xyz(P, cell, x, y, z);
-    R *dT = dst, *dY = dst + (long long)lbq::Q * P.N;
     bool solid = !far_from_head(P, H.hx_c, H.hy_c, x, y) && is_solid(P, H.hx_c, H.hy_c, x, y, z);
     double rY = rho_y[cell], rB = rho_b[cell];
     double ux = has_u ? u[3 * cell] : 0.0, uy = has_u ? u[3 * cell + 1] : 0.0, uz = has_u ? u[3 * cell + 2] : 0.0;
+    if constexpr (ST != ST_PLAIN) {
+        unsigned *d = reinterpret_cast<unsigned *>(dst_v);
+        for (int i = 0; i < lbq::Q; ++i) d[i * P.N + cell] = 0;
+        const double m[NMO] = {rY, rB, ux, uy, uz};
+        for (int k = 0; k < NMO; ++k) mo[k * P.N + cell] = solid ? 0.f : float(m[k]);
+        return;
+    }
+    R *dT = reinterpret_cast<R *>(dst_v), *dY = dT + (long long)lbq::Q * P.N;
     double uu = ux * ux + uy * uy + uz * uz;
     for (int i = 0; i < lbq::Q; ++i) {
         if (solid) {
@@ -134,8 +144,8 @@ __global__ __launch_bounds__(TPB) void k_init(DevParams P, const StepGeom *__res
 // Pull + moments of one cell at step t: moment set, colour fields, and into
 // acc the boundary fluxes of its pull (when fluxes) and, for a node the head
 // covers at t, its deleted mass.
-template <typename R>
-__device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &H, const R *__restrict__ src,
+template <typename R, typename PS>
+__device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &H, const PS &src,
                                              const R *__restrict__ mac, double *__restrict__ momd,
                                              R *__restrict__ mom, R *__restrict__ chi, long long cell, int x, int y,
                                              int z, bool first, bool fluxes, double (&acc)[NSLOT], int &any)
@@ -170,9 +180,9 @@ __device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &
 
 // Whole-box pull + moments (read-out path): writes this step's pending
 // boundary fluxes and deleted mass per block, touching no cumulative state.
-template <typename R>
+template <typename R, int ST>
 __global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__restrict__ G,
-                                                 const R *__restrict__ src, const R *__restrict__ mac,
+                                                 PopSrc<R, ST> src, const R *__restrict__ mac,
                                                  double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
                                                  double *__restrict__ slots, int first)
 {
@@ -195,9 +205,9 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__
 // boundary rule adds and the mass of nodes the head covers are added to the
 // block's cumulative slot.  Boxes 1 and 2 skip cells of box 0 (the head box)
 // so that no cell is counted twice.
-template <typename R>
+template <typename R, int ST>
 __global__ __launch_bounds__(TPB) void k_pre(DevParams P, const StepGeom *__restrict__ G,
-                                             const R *__restrict__ src, const R *__restrict__ mac,
+                                             PopSrc<R, ST> src, const R *__restrict__ mac,
                                              double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
                                              double *__restrict__ slots, int first)
 {
@@ -498,7 +508,7 @@ constexpr size_t ALIGN = 256;
 size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-    size_t pops, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, geo, total;
+    size_t pops, dmo, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, geo, total;
     long long nbm;   // blocks of the whole-box read-out kernels
     FusedGrid fg;    // tiling of the fused step kernel
     long long nbf;   // its block count
@@ -506,7 +516,9 @@ struct Layout {
     unsigned nb_wall;  // blocks of the wall-density kernel (grid-stride over the head box)
 };
 
-size_t real_size(int storage) { return storage == LB_F64 ? 8 : 4; }
+size_t real_size(int storage) { return storage == LB_F64 ? 8 : 4; }                    // arithmetic type
+size_t pop_size(int storage) { return storage == LB_F64 ? 8 : (storage == LB_F32 ? 4 : 2); }  // stored population
+bool reduced(int storage) { return storage == LB_BF16_DEV || storage == LB_F16_DEV; }
 
 // Fused kernel tile height per storage type (TY + 3 waves).  LDS: colour ring
 // 4 x 3 x 66 (TY + 2) values, state ring 2 x 64 TY x (2 FP64 + 10 values).
@@ -551,7 +563,9 @@ Layout layout_of(const lb_params &p)
     L.nbf = (long long)L.fg.ntx * L.fg.nty * L.fg.nzc;
     size_t off = 0;
     L.pops = off;
-    off += 2 * al(2 * lbq::Q * (size_t)N * rs);
+    off += 2 * al(2 * lbq::Q * (size_t)N * pop_size(p.storage));
+    L.dmo = off;  // source moments of the reduced storage forms (two copies)
+    if (reduced(p.storage)) off += 2 * al(NMO * (size_t)N * 4);
     L.momd = off;
     off += al(2 * (size_t)N * 8);
     L.mom = off;
@@ -586,7 +600,7 @@ const char *validate(const lb_params &p)
     if ((long long)p.nx * p.ny * p.nz > (1LL << 34)) return "box too large";
     if ((long long)p.nx * p.ny * p.nz * (long long)real_size(p.storage) >= (1LL << 32))
         return "box too large: one population plane must stay below 4 GiB";
-    if (p.storage != LB_F64 && p.storage != LB_F32) return "storage form not implemented (LB_F64 and LB_F32 only)";
+    if (p.storage < LB_F64 || p.storage > LB_F16_DEV) return "unknown storage form";
     if (!(p.tau_b > 0.5)) return "tau_b must exceed 1/2";
     if (p.rheology < 0 || p.rheology > 2) return "unknown rheology";
     if (p.rheology == LB_NEWTONIAN && !(p.tau_y > 0.5)) return "tau_y must exceed 1/2";
@@ -752,10 +766,31 @@ R *as(lb_handle *h, size_t off)
     return reinterpret_cast<R *>(h->ws + off);
 }
 
-template <typename R>
-R *pops_at(lb_handle *h, int which)
+// population copy `which` (0 / 1) and, for the reduced storage forms, the
+// source moments stored with it
+char *pops_at(lb_handle *h, int which)
 {
-    return as<R>(h, h->L.pops + which * al(2 * lbq::Q * (size_t)h->P.N * sizeof(R)));
+    return h->ws + h->L.pops + which * al(2 * lbq::Q * (size_t)h->P.N * pop_size(h->p.storage));
+}
+
+float *mo_at(lb_handle *h, int which)
+{
+    if (!reduced(h->p.storage)) return nullptr;
+    return as<float>(h, h->L.dmo + which * al(NMO * (size_t)h->P.N * 4));
+}
+
+template <typename R, int ST>
+PopSrc<R, ST> pop_src(lb_handle *h, int which)
+{
+    PopSrc<R, ST> s;
+    if constexpr (ST == ST_PLAIN) {
+        s.s = reinterpret_cast<const R *>(pops_at(h, which));
+    } else {
+        s.s = reinterpret_cast<const unsigned *>(pops_at(h, which));
+        s.mo = mo_at(h, which);
+    }
+    s.N = h->P.N;
+    return s;
 }
 
 StepGeom *geo(lb_handle *h) { return as<StepGeom>(h, h->L.geo); }
@@ -776,13 +811,13 @@ R *mac_at(lb_handle *h, long t)
 
 // Read-out pull: moments of the whole box at the current step, pending
 // fluxes / deletions / creations (nothing committed).
-template <typename R>
+template <typename R, int ST>
 lb_status run_readout(lb_handle *h)
 {
     const Layout &L = h->L;
     if (lb_status s = launch_clock(h)) return s;
-    hipLaunchKernelGGL(k_moments<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
-                       pops_at<R>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
+    hipLaunchKernelGGL((k_moments<R, ST>), dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
+                       pop_src<R, ST>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
                        as<R>(h, L.chi), as<double>(h, L.pend), h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
@@ -835,32 +870,35 @@ lb_status timing_mark(lb_handle *h, int k)
     return LB_OK;
 }
 
-template <typename R>
+template <typename R, int ST>
 lb_status launch_fused(lb_handle *h)
 {
     constexpr int TY = sizeof(R) == 8 ? TY_F64 : TY_F32;
     const Layout &L = h->L;
+    void *src = pops_at(h, h->cur), *dst = pops_at(h, 1 - h->cur);
     if constexpr (sizeof(R) == 4) {
         if (h->first)
-            hipLaunchKernelGGL((k_fused_pc<R, TY, true>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
-                               h->stream, h->P, geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
-                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
-                               mac_at<R>(h, h->t));
+            hipLaunchKernelGGL((k_fused_pc<R, TY, true, ST>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
+                               h->stream, h->P, geo(h), L.fg, src, dst, as<double>(h, L.momd), as<R>(h, L.mom),
+                               as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t), mo_at(h, h->cur),
+                               mo_at(h, 1 - h->cur));
         else
-            hipLaunchKernelGGL((k_fused_pc<R, TY, false>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
-                               h->stream, h->P, geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
-                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
-                               mac_at<R>(h, h->t));
+            hipLaunchKernelGGL((k_fused_pc<R, TY, false, ST>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
+                               h->stream, h->P, geo(h), L.fg, src, dst, as<double>(h, L.momd), as<R>(h, L.mom),
+                               as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t), mo_at(h, h->cur),
+                               mo_at(h, 1 - h->cur));
     } else {
+        static_assert(ST == ST_PLAIN, "FP64 storage is plain");
+        const R *s64 = reinterpret_cast<const R *>(src);
+        R *d64 = reinterpret_cast<R *>(dst);
         if (h->first)
             hipLaunchKernelGGL((k_fused<R, TY, true>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream, h->P,
-                               geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur), as<double>(h, L.momd),
-                               as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
+                               geo(h), L.fg, s64, d64, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                               as<R>(h, L.ghost), mac_at<R>(h, h->t));
         else
             hipLaunchKernelGGL((k_fused<R, TY, false>), dim3((unsigned)L.nbf), dim3((TY + 3) * 64), 0, h->stream,
-                               h->P, geo(h), L.fg, pops_at<R>(h, h->cur), pops_at<R>(h, 1 - h->cur),
-                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
-                               mac_at<R>(h, h->t));
+                               h->P, geo(h), L.fg, s64, d64, as<double>(h, L.momd), as<R>(h, L.mom),
+                               as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t));
     }
     return check_launch(h, "k_fused");
 }
@@ -871,14 +909,14 @@ lb_status launch_fused(lb_handle *h)
 // Every launch argument is the same at every step of one parity (the
 // population and macro buffers alternate), so an even number of steps can be
 // captured once and replayed.
-template <typename R>
+template <typename R, int ST>
 lb_status run_step(lb_handle *h)
 {
     const Layout &L = h->L;
     if (lb_status s = timing_mark(h, 0)) return s;
     if (lb_status s = launch_clock(h)) return s;
     if (h->p.has_nozzle || !h->P.periodic_z) {
-        hipLaunchKernelGGL(k_pre<R>, dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, geo(h), pops_at<R>(h, h->cur),
+        hipLaunchKernelGGL((k_pre<R, ST>), dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, geo(h), pop_src<R, ST>(h, h->cur),
                            mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
                            as<double>(h, L.cumpre), h->first);
         if (lb_status s = check_launch(h, "k_pre")) return s;
@@ -900,7 +938,7 @@ lb_status run_step(lb_handle *h)
         if (lb_status s = check_launch(h, "k_ghost")) return s;
     }
     if (lb_status s = timing_mark(h, 1)) return s;
-    if (lb_status s = launch_fused<R>(h)) return s;
+    if (lb_status s = launch_fused<R, ST>(h)) return s;
     if (lb_status s = timing_mark(h, 2)) return s;
     hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, h->stream, geo(h));
     if (lb_status s = check_launch(h, "k_tick")) return s;
@@ -918,15 +956,14 @@ lb_status run_output(lb_handle *h, O *ry, O *rb, O *u)
     return check_launch(h, "k_output");
 }
 
-template <typename R>
+template <typename R, int ST>
 lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype, lb_conserved *cons)
 {
     const Layout &L = h->L;
     const long long N = h->P.N;
-    if (lb_status s = run_readout<R>(h)) return s;
+    if (lb_status s = run_readout<R, ST>(h)) return s;
     // outputs: direct to device pointers, or staged in the spare population buffer
-    size_t psz = al(2 * lbq::Q * (size_t)N * sizeof(R));
-    char *stage = h->ws + L.pops + (1 - h->cur) * psz;
+    char *stage = pops_at(h, 1 - h->cur);
     size_t osz = dtype == 0 ? 8 : 4;
     void *dry = ry, *drb = rb, *du = u;
     if (!dst_dev) {
@@ -970,6 +1007,29 @@ lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, i
     return LB_OK;
 }
 
+// Call f.operator()<R, ST>() for the handle's storage form: R the arithmetic
+// type, ST the stored representation.
+template <typename F>
+lb_status with_storage(lb_handle *h, F &&f)
+{
+    switch (h->p.storage) {
+    case LB_F64: return f.template operator()<double, ST_PLAIN>();
+    case LB_F32: return f.template operator()<float, ST_PLAIN>();
+    case LB_BF16_DEV: return f.template operator()<float, ST_BF16>();
+    default: return f.template operator()<float, ST_F16>();
+    }
+}
+
+lb_status step_one(lb_handle *h)
+{
+    return with_storage(h, [&]<typename R, int ST>() { return run_step<R, ST>(h); });
+}
+
+lb_status moments_any(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype, lb_conserved *cons)
+{
+    return with_storage(h, [&]<typename R, int ST>() { return moments_impl<R, ST>(h, ry, rb, u, dst_dev, dtype, cons); });
+}
+
 // ---------------------------------------------------------------- batching
 
 constexpr size_t MAX_CHAINS = 4;
@@ -998,7 +1058,7 @@ lb_status chain_exec(lb_handle *h, int k, hipGraphExec_t *out)
     h->stream = h->cap;
     lb_status st = LB_OK;
     for (int j = 0; j < k && st == LB_OK; ++j)
-        st = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
+        st = step_one(h);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap, &g);
     h->stream = saved;
@@ -1029,7 +1089,7 @@ lb_status chain_exec(lb_handle *h, int k, hipGraphExec_t *out)
 lb_status step_eager(lb_handle *h, int n)
 {
     for (int j = 0; j < n; ++j) {
-        lb_status s = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
+        lb_status s = step_one(h);
         if (s) return s;
     }
     return LB_OK;
@@ -1067,10 +1127,9 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     h->first = 1;
     h->unstable = 0;
     const long long N = h->P.N;
-    const size_t rs = real_size(p->storage);
-    size_t psz = al(2 * lbq::Q * (size_t)N * rs);
-    // stage the initial fields in the second population buffer
-    char *stage = h->ws + L.pops + psz;
+    // stage the initial fields in the second population buffer (at least
+    // 76 B per cell, the fields need 40)
+    char *stage = pops_at(h, 1);
     double *dry = reinterpret_cast<double *>(stage);
     double *drb = dry + N;
     double *du = drb + N;
@@ -1091,12 +1150,11 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     }
     dim3 grid((unsigned)L.nbm);
     hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, h->stream, h->P, geo(h));
-    if (p->storage == LB_F64)
-        hipLaunchKernelGGL(k_init<double>, grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
-                           as<double>(h, L.pops));
-    else
-        hipLaunchKernelGGL(k_init<float>, grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
-                           as<float>(h, L.pops));
+    with_storage(h, [&]<typename R, int ST>() {
+        hipLaunchKernelGGL((k_init<R, ST>), grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
+                           (void *)pops_at(h, 0), mo_at(h, 0));
+        return LB_OK;
+    });
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
@@ -1113,12 +1171,11 @@ lb_status lb_step(lb_handle *h, int nsteps)
     if (!h || nsteps < 0) return fail(h, LB_EINVAL, "bad handle or step count");
     if (h->unstable) return fail(h, LB_ESTATE, "handle is unstable; only lb_moments and lb_destroy are allowed");
     for (int n = 0; n < nsteps; ++n) {
-        lb_status s = h->p.storage == LB_F64 ? run_step<double>(h) : run_step<float>(h);
+        lb_status s = step_one(h);
         if (s) return s;
         if (h->p.check_interval > 0 && h->t % h->p.check_interval == 0) {
             lb_conserved c;
-            s = h->p.storage == LB_F64 ? moments_impl<double>(h, nullptr, nullptr, nullptr, 1, 0, &c)
-                                       : moments_impl<float>(h, nullptr, nullptr, nullptr, 1, 0, &c);
+            s = moments_any(h, nullptr, nullptr, nullptr, 1, 0, &c);
             if (s) return s;
         }
     }
@@ -1128,8 +1185,7 @@ lb_status lb_step(lb_handle *h, int nsteps)
 lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype, lb_conserved *cons)
 {
     if (!h || (dtype != 0 && dtype != 1)) return fail(h, LB_EINVAL, "bad handle or dtype");
-    return h->p.storage == LB_F64 ? moments_impl<double>(h, rho_y, rho_b, u, dst_is_device, dtype, cons)
-                                  : moments_impl<float>(h, rho_y, rho_b, u, dst_is_device, dtype, cons);
+    return moments_any(h, rho_y, rho_b, u, dst_is_device, dtype, cons);
 }
 
 long lb_time(const lb_handle *h) { return h ? h->t : -1; }

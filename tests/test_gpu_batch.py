@@ -20,6 +20,7 @@ CASES = [
     small_print((40, 32, 24), (12.0, 15.5), 4.0, 10.0, (0.03, 0.011), 0.02, 0.5, "f32"),
     small_print((37, 23, 19), (8.0, 9.0), 3.0, 8.0, (0.02, 0.0), 0.015, 0.7, "f32"),
     small_print((64, 48, 32), (20.0, 24.0), 5.0, 12.0, (0.0, 0.01), 0.01, 0.4, "f64"),
+    small_print((48, 40, 28), (16.0, 20.0), 4.0, 10.0, (0.015, 0.005), 0.012, 0.6, "bf16dev"),
 ]
 
 
@@ -38,7 +39,7 @@ def assert_same(a, b, what):
 def test_batch_equals_alone():
     from paper_2102_02655_amd import lbprint as LB
 
-    steps = [(7, 6, 9), (10, 10, 10), (3, 8, 2)]  # per call, per case: odd counts and first steps included
+    steps = [(7, 6, 9, 5), (10, 10, 10, 10), (3, 8, 2, 4)]  # per call, per case: odd counts and first steps
     alone = [LB.Sim(cfg, ry, rb) for cfg, ry, rb in CASES]
     mixed = [LB.Sim(cfg, ry, rb) for cfg, ry, rb in CASES]
     for call in steps:
