@@ -60,7 +60,6 @@ def test_footprint_scales_with_storage(lib):
 
 @pytest.mark.parametrize("change,msg", [
     (dict(tau_b=0.5), "tau_b"),
-    (dict(storage="bf16dev"), "storage"),
     (dict(face_zlo="wall", face_zhi="periodic"), "z faces"),
     (dict(rheology="power_law", K=0.0), "power law"),
     (dict(rheology="power_law", K=1e-3, n=1.5), "power law"),
@@ -112,3 +111,23 @@ def test_step_batch_rejects_bad_arguments_without_touching_the_gpu(lib):
     assert lib.lb_step_batch(hs, ks, 1) == LB.LB_EINVAL
     assert lib.lb_step_batch(hs, ks, 0) == LB.LB_EINVAL
     assert b"lb_step_batch" in lib.lb_last_error(None)
+
+
+def test_unknown_storage_code_rejected(lib):
+    cfg = W.static_droplet(n=8, radius=2.0)[0]
+    p = LB.make_params(cfg)
+    p.storage = 9
+    n = C.c_size_t()
+    assert lib.lb_footprint(C.byref(p), C.byref(n)) == LB.LB_EINVAL
+    assert b"storage" in lib.lb_last_error(None)
+
+
+def test_reduced_storage_footprint():
+    """16-bit deviations (76 B) plus FP32 moments (20 B) per cell and copy,
+    against 152 B per cell and copy for FP32 populations."""
+    c32 = W.print_bed(storage="f32")
+    n = 512 * 256 * 128
+    for st in ("bf16dev", "f16dev"):
+        b = LB.footprint(dict(c32, storage=st))
+        assert b < LB.footprint(c32)
+        assert b > 2 * (76 + 20) * n
