@@ -22,6 +22,8 @@
 // (or of rho_Y / rho in the recolouring) would not average out but drift.
 #pragma once
 
+#include <utility>
+
 #include <hip/hip_runtime.h>
 
 #include "d3q19.h"
@@ -264,15 +266,32 @@ struct PopSrc {
     const unsigned *s;
     const float *mo;  // NMO x N source moments
     long long N;
+    // what a link needs from memory: the packed word of population plane
+    // `plane` at `cell` and that cell's moments; decoded for link I
+    struct Raw {
+        unsigned w;
+        float m[NMO];
+    };
+    __device__ __forceinline__ Raw load_raw(int plane, long long cell) const
+    {
+        Raw r;
+        r.w = s[plane * N + cell];
+#pragma unroll
+        for (int k = 0; k < NMO; ++k) r.m[k] = mo[k * N + cell];
+        return r;
+    }
+    template <int I>
+    __device__ __forceinline__ void finish(const DevParams &P, const Raw &r, float &T, float &Y) const
+    {
+        float fT, fY;
+        feq_TY<I>(P, r.m[0], r.m[1], r.m[2], r.m[3], r.m[4], fT, fY);
+        T = fT + decode_dev<ST, I>((unsigned short)(r.w & 0xFFFFu));
+        Y = fY + decode_dev<ST, I>((unsigned short)(r.w >> 16));
+    }
     template <int I>
     __device__ __forceinline__ void get(const DevParams &P, long long cell, float &T, float &Y) const
     {
-        const unsigned wd = s[I * N + cell];
-        const unsigned short dT = (unsigned short)(wd & 0xFFFFu), dY = (unsigned short)(wd >> 16);
-        float fT, fY;
-        feq_TY<I>(P, mo[cell], mo[N + cell], mo[2 * N + cell], mo[3 * N + cell], mo[4 * N + cell], fT, fY);
-        T = fT + decode_dev<ST, I>(dT);
-        Y = fY + decode_dev<ST, I>(dY);
+        finish<I>(P, load_raw(I, cell), T, Y);
     }
 };
 
@@ -280,6 +299,19 @@ template <typename R>
 struct PopSrc<R, ST_PLAIN> {
     const R *s;
     long long N;
+    struct Raw {
+        R T, Y;
+    };
+    __device__ __forceinline__ Raw load_raw(int plane, long long cell) const
+    {
+        return Raw{s[plane * N + cell], s[(lbq::Q + plane) * N + cell]};
+    }
+    template <int I>
+    __device__ __forceinline__ void finish(const DevParams &, const Raw &r, R &T, R &Y) const
+    {
+        T = r.T;
+        Y = r.Y;
+    }
     template <int I>
     __device__ __forceinline__ void get(const DevParams &, long long cell, R &T, R &Y) const
     {
@@ -288,40 +320,19 @@ struct PopSrc<R, ST_PLAIN> {
     }
 };
 
-// Pull of one population pair (Eq. (lbm) as a pull): f_i(x, t) comes from
-// x - c_i at t-1, or, when that site is not fluid at t-1, from the boundary
-// rule applied to x's own post-collision population of the opposite link
+// Boundary rule of link I (Eq. (lbm) as a pull): f_i(x, t) comes from x - c_i
+// at t-1 unless that site is not fluid at t-1; then from the rule applied to
+// x's own post-collision population of the opposite link, (Tout, Yout)
 // (Sec. II.B: halfway bounce-back, Eq. (movwall) with the wall density
 // extrapolated inward, Eq. (movnozzle) on the lid, anti-bounce-back on
-// pressure faces).
-template <typename R, int I, bool FULL = true, typename PS>
-__device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, const PS &src,
-                                         const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
-                                         bool first, Mom<R> &M, Flux &fl)
+// pressure faces).  st: the class of x - c_i.
+template <typename R, int I, bool FULL = true>
+__device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, const R *__restrict__ mac, int x,
+                                          int y, int z, long long cell, bool near, int st, R Tout, R Yout, Mom<R> &M,
+                                          Flux &fl)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    constexpr int IB = lbq::opp(I);
     const long long N = P.N;
-    if (first) {
-        R T0, Y0;
-        src.template get<I>(P, cell, T0, Y0);
-        mom_add<R, I, FULL>(M, T0, Y0);
-        return;
-    }
-    int xs = X ? wrap(x - X, P.nx) : x;
-    int ys = Yc ? wrap(y - Yc, P.ny) : y;
-    int zs = z - Z;
-    int st = (Z == 0 && !near) ? ST_FLUID : classify(P, H.hx_p, H.hy_p, xs, ys, zs, near);
-    if (st == ST_FLUID) {
-        long long sc = ((long long)zs * P.ny + ys) * P.nx + xs;
-        R T0, Y0;
-        src.template get<I>(P, sc, T0, Y0);
-        mom_add<R, I, FULL>(M, T0, Y0);
-        return;
-    }
-    // the link from x towards the wall is IB; its post-collision values
-    R Tout, Yout;
-    src.template get<IB>(P, cell, Tout, Yout);
     const R wi = R(lbq::w(I));
     R T, Yv;
     if (st == ST_OPEN_LO || st == ST_OPEN_HI) {
@@ -411,15 +422,51 @@ __device__ __forceinline__ void pull_one(const DevParams &P, const HeadPos &H, c
     mom_add<R, I, FULL>(M, T, Yv);
 }
 
-template <typename R, bool FULL = true, int I = 0, typename PS>
+// Pull of all links of one cell with the boundary rules.  Every link is
+// classified first and its population read (from x - c_i, or x's own
+// opposite link at a boundary) before any rule is applied, so the reads are
+// in flight together; then the rules and the moments, link by link in order.
+template <typename R, bool FULL = true, typename PS>
 __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, const PS &src,
                                          const R *__restrict__ mac, int x, int y, int z, long long cell, bool near,
                                          bool first, Mom<R> &M, Flux &fl)
 {
-    if constexpr (I < lbq::Q) {
-        pull_one<R, I, FULL>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
-        pull_all<R, FULL, I + 1>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
-    }
+    typename PS::Raw raw[lbq::Q];
+    int st[lbq::Q];
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        (
+            [&] {
+                constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+                int s_ = ST_FLUID, plane = I;
+                long long sc = cell;
+                if (!first) {
+                    const int xs = X ? wrap(x - X, P.nx) : x;
+                    const int ys = Yc ? wrap(y - Yc, P.ny) : y;
+                    int zs = z - Z;  // classify wraps it when z is periodic
+                    s_ = (Z == 0 && !near) ? ST_FLUID : classify(P, H.hx_p, H.hy_p, xs, ys, zs, near);
+                    const long long scf = ((long long)zs * P.ny + ys) * P.nx + xs;
+                    sc = s_ == ST_FLUID ? scf : cell;
+                    plane = s_ == ST_FLUID ? I : lbq::opp(I);
+                }
+                st[I] = s_;
+                raw[I] = src.load_raw(plane, sc);
+            }(),
+            ...);
+    }(std::make_integer_sequence<int, lbq::Q>{});
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        (
+            [&] {
+                R T, Y;
+                if (st[I] == ST_FLUID) {
+                    src.template finish<I>(P, raw[I], T, Y);
+                    mom_add<R, I, FULL>(M, T, Y);
+                } else {
+                    src.template finish<lbq::opp(I)>(P, raw[I], T, Y);
+                    pull_rule<R, I, FULL>(P, H, mac, x, y, z, cell, near, st[I], T, Y, M, fl);
+                }
+            }(),
+            ...);
+    }(std::make_integer_sequence<int, lbq::Q>{});
 }
 
 // A uniform (scalar) value the optimiser must treat as new at this point:

@@ -156,7 +156,7 @@ __device__ __forceinline__ bool macro_needed(const DevParams &P, const HeadPos &
 }
 
 template <typename R, int TY, bool FIRST>
-__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, const StepGeom *__restrict__ G,
+__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeom *__restrict__ G,
                                                             FusedGrid FG, const R *__restrict__ src,
                                                             R *__restrict__ dst,
                                                             const double *__restrict__ momd,
@@ -166,6 +166,12 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, const S
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     const HeadPos H = G->H;
     const Box3 head = G->bx[0];
+    // the last kernel of the step advances the device step counter (the
+    // fields read above are not written by it)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        G->t += 1;
+        G->first = 0;
+    }
     __shared__ R chi_l[4][3][PL];
     __shared__ double st_d[2][2][NI];
     __shared__ R st_r[2][10][NI];
@@ -369,7 +375,7 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, const S
 // plane.  Loads and stores are issued by different waves, so neither waits
 // behind the other in a wave's queue of outstanding memory operations.
 template <typename R, int TY, bool FIRST, int ST = ST_PLAIN>
-__global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, const StepGeom *__restrict__ G,
+__global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, StepGeom *__restrict__ G,
                                                                   FusedGrid FG, const void *__restrict__ src,
                                                                   void *__restrict__ dst,
                                                                   const double *__restrict__ momd,
@@ -390,6 +396,12 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
     __shared__ float mring[ST == ST_PLAIN ? 1 : 4][NMO][ST == ST_PLAIN ? 1 : MR];
     const HeadPos H = G->H;
     const Box3 head = G->bx[0];
+    // the last kernel of the step advances the device step counter (the
+    // fields read above are not written by it)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        G->t += 1;
+        G->first = 0;
+    }
     __shared__ R chi_l[4][3][PL];
     __shared__ double mo_d[4][2][NI];      // masses delta rho, rho_Y (FP64)
     __shared__ R mo_r[4][NMOMR][NI];       // the other raw moments m[2..16]
@@ -423,6 +435,19 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
             if (tile && c >= z0 && st_ok[c & 3][ii]) {
                 const int ss = c & 3;
                 const int sm = (c + 3) & 3, s0 = c & 3, sp1 = (c + 1) & 3;
+                // the local relaxation time first, then the colour stencil:
+                // the solve's temporaries and the stencil's reads do not
+                // overlap (register pressure)
+                CellState<R> C;
+                {
+                    Mom<R> M;
+                    M.dm[0] = mo_d[ss][0][ii];
+                    M.dm[1] = mo_d[ss][1][ii];
+#pragma unroll
+                    for (int m = 2; m < NMOM; ++m) M.m[m] = mo_r[ss][m - 2][ii];
+                    C = cell_state<R>(P, M);
+                }
+                __builtin_amdgcn_sched_barrier(0);
                 Grad<R> G;
 #pragma unroll
                 for (int m = 0; m < 9; ++m) G.g[m] = R(0);
@@ -441,12 +466,7 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
                         if (Z) G.g[3 * f + 2] += Z > 0 ? d : -d;
                     }
                 }
-                Mom<R> M;
-                M.dm[0] = mo_d[ss][0][ii];
-                M.dm[1] = mo_d[ss][1][ii];
-#pragma unroll
-                for (int m = 2; m < NMOM; ++m) M.m[m] = mo_r[ss][m - 2][ii];
-                const CellState<R> C = cell_state<R>(P, M);
+                __builtin_amdgcn_sched_barrier(0);
                 const long long ccell = col_off + (long long)c * plane_sz;
                 R rY, rB, u[3];
                 collide_state<R, ST>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,

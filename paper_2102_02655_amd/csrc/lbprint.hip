@@ -32,8 +32,8 @@ using namespace lbk;
 namespace {
 
 constexpr int TPB = 256;       // threads per block of the per-cell kernels
-constexpr int NB_SPARSE = 64;  // fixed grid of the head-box kernels (deterministic slots)
-constexpr int NB_PRE = 512;    // fixed grid of the boundary preparation kernel
+constexpr int NB_SPARSE = 256;  // fixed grid of the head-box kernels (deterministic slots)
+constexpr int NB_PRE = 2048;    // fixed grid of the boundary preparation kernel
 constexpr int NSLOT = 6;       // per-block FP64 sums: wall Y, wall B, open Y, open B, deleted Y, deleted B
 constexpr int NPART = 6;       // per-block FP64 sums of the output: mass Y, B, momentum xyz, unstable
 
@@ -206,14 +206,20 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__
 // block's cumulative slot.  Boxes 1 and 2 skip cells of box 0 (the head box)
 // so that no cell is counted twice.
 template <typename R, int ST>
-__global__ __launch_bounds__(TPB) void k_pre(DevParams P, const StepGeom *__restrict__ G,
-                                             PopSrc<R, ST> src, const R *__restrict__ mac,
-                                             double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
-                                             double *__restrict__ slots, int first)
+__global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__ G, PopSrc<R, ST> src,
+                                             const R *__restrict__ mac, double *__restrict__ momd,
+                                             R *__restrict__ mom, R *__restrict__ chi, double *__restrict__ slots,
+                                             int first)
 {
-    const HeadPos H = G->H;
-    const Box3 b0 = G->bx[0], b1 = G->bx[1], b2 = G->bx[2];
-    const int nbox = G->nbox;
+    // the step's geometry from the device step counter (every block), kept
+    // in memory by block 0 for the step's later kernels
+    __shared__ StepGeom sg;
+    if (threadIdx.x == 0) make_geom(P, G->t, G->first, sg);
+    __syncthreads();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *G = sg;
+    const HeadPos H = sg.H;
+    const Box3 b0 = sg.bx[0], b1 = sg.bx[1], b2 = sg.bx[2];
+    const int nbox = sg.nbox;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
     int any = 0;
     for (int bi = 0; bi < nbox; ++bi) {
@@ -439,15 +445,6 @@ __global__ void k_clock(DevParams P, StepGeom *__restrict__ G)
         StepGeom g;
         make_geom(P, G->t, G->first, g);
         *G = g;
-    }
-}
-
-// End of a step: advance the device step counter.
-__global__ void k_tick(StepGeom *__restrict__ G)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        G->t += 1;
-        G->first = 0;
     }
 }
 
@@ -914,7 +911,8 @@ lb_status run_step(lb_handle *h)
 {
     const Layout &L = h->L;
     if (lb_status s = timing_mark(h, 0)) return s;
-    if (lb_status s = launch_clock(h)) return s;
+    if (!h->p.has_nozzle && h->P.periodic_z)
+        if (lb_status s = launch_clock(h)) return s;  // otherwise k_pre computes the geometry
     if (h->p.has_nozzle || !h->P.periodic_z) {
         hipLaunchKernelGGL((k_pre<R, ST>), dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, geo(h), pop_src<R, ST>(h, h->cur),
                            mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
@@ -940,8 +938,6 @@ lb_status run_step(lb_handle *h)
     if (lb_status s = timing_mark(h, 1)) return s;
     if (lb_status s = launch_fused<R, ST>(h)) return s;
     if (lb_status s = timing_mark(h, 2)) return s;
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, h->stream, geo(h));
-    if (lb_status s = check_launch(h, "k_tick")) return s;
     h->cur = 1 - h->cur;
     h->t += 1;
     h->first = 0;
