@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # once and written once; the reduced forms also read and write the cell's
 # five FP32 moments (2 x (38 x 2 + 5 x 4) B).
 BYTES_PER_LU = {"f64": 608, "f32": 304, "bf16dev": 192, "f16dev": 192}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_print_bed_512x256x128_f32_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_pc_print_bed_512x256x128_f32_traffic.md")
 
 
 def source_digest() -> str:
@@ -207,7 +207,7 @@ def main():
                    "cells": cells, "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused", "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
+                     "kernel": "k_fused_pc", "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
                      "prep_ms": tm["prep_ms"] / max(tm["steps"], 1),
                      "whole_step_GBs": bpl * mlups * 1e6 / 1e9},
         "mass": list(map(float, cons["mass"])),

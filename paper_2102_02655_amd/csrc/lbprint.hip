@@ -255,19 +255,29 @@ __global__ __launch_bounds__(TPB) void k_create(DevParams P, const StepGeom *__r
         int x = ((bx0 + ix) % P.nx + P.nx) % P.nx, y = ((by0 + iy) % P.ny + P.ny) % P.ny, z = bz0 + iz;
         if (z < 0 || z >= P.nz) continue;
         if (!is_solid(P, H.hx_p, H.hy_p, x, y, z) || is_solid(P, H.hx_c, H.hy_c, x, y, z)) continue;
-        double sY = 0.0, sB = 0.0;
-        int cnt = 0;
+        // the neighbours fluid at both steps, all classified before any read
+        // (the reads are in flight together); others add an exact zero
+        long long nc[lbq::Q];
+        bool use[lbq::Q];
+#pragma unroll
         for (int i = 1; i < lbq::Q; ++i) {
             int zz = z + lbq::cz(i);
             if (P.periodic_z) zz = wrap(zz, P.nz);
-            if (zz < 0 || zz >= P.nz) continue;
+            const bool in = zz >= 0 && zz < P.nz;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
-            if (is_solid(P, H.hx_p, H.hy_p, xx, yy, zz) || is_solid(P, H.hx_c, H.hy_c, xx, yy, zz)) continue;
-            double rY, rB;
-            dens(P, momd, cidx(P, xx, yy, zz), rY, rB);
-            sY += rY;
-            sB += rB;
-            ++cnt;
+            use[i] = in && !is_solid(P, H.hx_p, H.hy_p, xx, yy, zz) && !is_solid(P, H.hx_c, H.hy_c, xx, yy, zz);
+            nc[i] = use[i] ? cidx(P, xx, yy, zz) : cidx(P, x, y, z);
+        }
+        double nd[lbq::Q][2];
+#pragma unroll
+        for (int i = 1; i < lbq::Q; ++i) dens(P, momd, nc[i], nd[i][0], nd[i][1]);
+        double sY = 0.0, sB = 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int i = 1; i < lbq::Q; ++i) {
+            sY += use[i] ? nd[i][0] : 0.0;
+            sB += use[i] ? nd[i][1] : 0.0;
+            cnt += use[i] ? 1 : 0;
         }
         double rY = cnt ? sY / cnt : 0.0, rB = cnt ? sB / cnt : P.rho0[1];
         long long cell = cidx(P, x, y, z);
@@ -304,19 +314,29 @@ __global__ __launch_bounds__(TPB) void k_wall(DevParams P, const StepGeom *__res
         int x = ((bx0 + ix) % P.nx + P.nx) % P.nx, y = ((by0 + iy) % P.ny + P.ny) % P.ny, z = bz0 + iz;
         if (z < 0 || z >= P.nz) continue;
         if (!is_solid(P, H.hx_c, H.hy_c, x, y, z)) continue;
-        double nY = 0.0, nB = 0.0, den = 0.0;
+        // the fluid neighbours, all classified before any read (the reads
+        // are in flight together); others add an exact zero
+        long long nc[lbq::Q];
+        bool use[lbq::Q];
+#pragma unroll
         for (int i = 1; i < lbq::Q; ++i) {
             int zz = z + lbq::cz(i);
             if (P.periodic_z) zz = wrap(zz, P.nz);
-            if (zz < 0 || zz >= P.nz) continue;
+            const bool in = zz >= 0 && zz < P.nz;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
-            if (is_solid(P, H.hx_c, H.hy_c, xx, yy, zz)) continue;
-            double wi = lbq::w(i);
-            double rY, rB;
-            dens(P, momd, cidx(P, xx, yy, zz), rY, rB);
-            nY += wi * rY;
-            nB += wi * rB;
-            den += wi;
+            use[i] = in && !is_solid(P, H.hx_c, H.hy_c, xx, yy, zz);
+            nc[i] = use[i] ? cidx(P, xx, yy, zz) : cidx(P, x, y, z);
+        }
+        double nd[lbq::Q][2];
+#pragma unroll
+        for (int i = 1; i < lbq::Q; ++i) dens(P, momd, nc[i], nd[i][0], nd[i][1]);
+        double nY = 0.0, nB = 0.0, den = 0.0;
+#pragma unroll
+        for (int i = 1; i < lbq::Q; ++i) {
+            const double wi = lbq::w(i);
+            nY += use[i] ? wi * nd[i][0] : 0.0;
+            nB += use[i] ? wi * nd[i][1] : 0.0;
+            den += use[i] ? wi : 0.0;
         }
         long long cell = cidx(P, x, y, z);
         double sY = den > 0.0 ? P.zeta_noz[0] * nY / den : 0.0;
