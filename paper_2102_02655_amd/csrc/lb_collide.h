@@ -51,42 +51,96 @@ struct OutCoef {
     double fracY;
 };
 
+// The quadratic form of OutCoef grouped by lattice axis and plane, formed
+// once per cell: every moving link's bracket is then one addition,
+//   axis link  +-e_a        : s_a +- a_a,              s_a = k1 + B_aa
+//   plane link (sa, sb) in ab: (s_ab + sa sb B_ab) + sa (a_a + sa sb a_b),
+// s_ab = k1 + B_aa + B_bb, and the recolouring sum c_i.r likewise.
+template <typename R>
+struct LinkSums {
+    R t0;
+    R s[3], a[3], r[3];
+    R p[3], m[3];    // s_ab + B_ab, s_ab - B_ab  (ab = xy, xz, yz)
+    R ap[3], am[3];  // a_a + a_b, a_a - a_b
+    R rp[3], rm[3];  // r_a + r_b, r_a - r_b
+    double fracY;
+};
+
+template <typename R>
+__device__ __forceinline__ LinkSums<R> link_sums(const OutCoef<R> &K)
+{
+    LinkSums<R> L;
+    L.t0 = K.t0;
+    const R b[3] = {K.bxx, K.byy, K.bzz}, a[3] = {K.ax, K.ay, K.az}, r[3] = {K.rx, K.ry, K.rz};
+    const R bo[3] = {K.bxy, K.bxz, K.byz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        L.s[d] = K.k1 + b[d];
+        L.a[d] = a[d];
+        L.r[d] = r[d];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int da = q < 2 ? 0 : 1, db = q == 0 ? 1 : 2;
+        const R sab = L.s[da] + b[db];
+        L.p[q] = sab + bo[q];
+        L.m[q] = sab - bo[q];
+        L.ap[q] = a[da] + a[db];
+        L.am[q] = a[da] - a[db];
+        L.rp[q] = r[da] + r[db];
+        L.rm[q] = r[da] - r[db];
+    }
+    L.fracY = K.fracY;
+    return L;
+}
+
+// Post-collision T value of link I and its recolouring term w_i c_i.r/|c_i|.
+template <typename R, int I>
+__device__ __forceinline__ void link_value(const LinkSums<R> &L, R &Tst, R &cgw)
+{
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+    constexpr int nz = (X != 0) + (Yc != 0) + (Z != 0);
+    if constexpr (I == 0) {
+        Tst = L.t0;
+        cgw = R(0);
+    } else {
+        const R wi = R(lbq::w(I));
+        R q, cg;
+        if constexpr (nz == 1) {
+            constexpr int d = X ? 0 : (Yc ? 1 : 2);
+            constexpr int sg = X + Yc + Z;
+            q = L.s[d] + (sg > 0 ? L.a[d] : -L.a[d]);
+            cg = sg > 0 ? L.r[d] : -L.r[d];
+        } else {
+            // plane ab with components (sa, sb)
+            constexpr int q_ = Z == 0 ? 0 : (Yc == 0 ? 1 : 2);
+            constexpr int sa = q_ == 2 ? Yc : X, sb = Z == 0 ? Yc : Z;
+            const R base = sa * sb > 0 ? L.p[q_] : L.m[q_];
+            const R av = sa * sb > 0 ? L.ap[q_] : L.am[q_];
+            const R rv = sa * sb > 0 ? L.rp[q_] : L.rm[q_];
+            q = base + (sa > 0 ? av : -av);
+            cg = sa > 0 ? rv : -rv;
+        }
+        Tst = wi * q;
+        cgw = (wi * R(lbq::inv_len(I))) * cg;
+    }
+}
+
 // Store of link I into the population planes pT (set T) and pY (set Y) at
 // byte offset cellb.  The next step reads these once, a full sweep later, so
 // the stores are non-temporal.
 template <typename R, int I>
-__device__ __forceinline__ void store_one(const DevParams &P, const OutCoef<R> &K, gchar *pT, gchar *pY,
+__device__ __forceinline__ void store_one(const DevParams &P, const LinkSums<R> &L, gchar *pT, gchar *pY,
                                           unsigned cellb)
 {
     typedef __attribute__((address_space(1))) R gR;
-    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    R Tst, cgw = R(0);
-    if constexpr (I == 0) {
-        Tst = K.t0;
-    } else {
-        R q = K.k1;
-        if (X) q += X > 0 ? K.ax : -K.ax;
-        if (Yc) q += Yc > 0 ? K.ay : -K.ay;
-        if (Z) q += Z > 0 ? K.az : -K.az;
-        if (X) q += K.bxx;
-        if (Yc) q += K.byy;
-        if (Z) q += K.bzz;
-        if (X && Yc) q += X * Yc > 0 ? K.bxy : -K.bxy;
-        if (X && Z) q += X * Z > 0 ? K.bxz : -K.bxz;
-        if (Yc && Z) q += Yc * Z > 0 ? K.byz : -K.byz;
-        const R wi = R(lbq::w(I));
-        Tst = wi * q;
-        R cg = R(0);
-        if (X) cg += X > 0 ? K.rx : -K.rx;
-        if (Yc) cg += Yc > 0 ? K.ry : -K.ry;
-        if (Z) cg += Z > 0 ? K.rz : -K.rz;
-        cgw = wi * R(lbq::inv_len(I)) * cg;
-    }
+    R Tst, cgw;
+    link_value<R, I>(L, Tst, cgw);
     // the ink's share fracY (w_i rho_ref + T_i) + recolouring, formed in FP64
     // so that sum_i f^Y_i = rho_Y holds to the final rounding of each stored
     // value (an FP32 fracY, or any FP32 rounding of fracY T_i, would bias
     // every cell of a uniform region alike)
-    const R Yst = R(__builtin_fma(K.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
+    const R Yst = R(__builtin_fma(L.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
     __builtin_nontemporal_store(Tst, reinterpret_cast<gR *>(pT + cellb));
     __builtin_nontemporal_store(Yst, reinterpret_cast<gR *>(pY + cellb));
 }
@@ -97,10 +151,11 @@ template <typename R>
 __device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &K, gchar *base,
                                           unsigned long long pstride, unsigned cellb)
 {
+    const LinkSums<R> L = link_sums(K);
     gchar *pT = base;
     gchar *pY = base + (unsigned long long)lbq::Q * pstride;
     [&]<int... I>(std::integer_sequence<int, I...>) {
-        ((store_one<R, I>(P, K, pT + (unsigned long long)I * pstride, pY + (unsigned long long)I * pstride, cellb)),
+        ((store_one<R, I>(P, L, pT + (unsigned long long)I * pstride, pY + (unsigned long long)I * pstride, cellb)),
          ...);
     }(std::make_integer_sequence<int, lbq::Q>{});
 }
@@ -109,34 +164,13 @@ __device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &
 // post-collision moments (rho_Y, rho_B, u'), 16-bit (the deviation is the
 // non-equilibrium, perturbation and recolouring part of the compact form).
 template <int ST, int I>
-__device__ __forceinline__ void store_one_dev(const DevParams &P, const OutCoef<float> &K, float rY, float rB,
+__device__ __forceinline__ void store_one_dev(const DevParams &P, const LinkSums<float> &L, float rY, float rB,
                                               float vx, float vy, float vz, gchar *pw, unsigned cellb)
 {
     typedef __attribute__((address_space(1))) unsigned gU;
-    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    float Tst, cgw = 0.f;
-    if constexpr (I == 0) {
-        Tst = K.t0;
-    } else {
-        float q = K.k1;
-        if (X) q += X > 0 ? K.ax : -K.ax;
-        if (Yc) q += Yc > 0 ? K.ay : -K.ay;
-        if (Z) q += Z > 0 ? K.az : -K.az;
-        if (X) q += K.bxx;
-        if (Yc) q += K.byy;
-        if (Z) q += K.bzz;
-        if (X && Yc) q += X * Yc > 0 ? K.bxy : -K.bxy;
-        if (X && Z) q += X * Z > 0 ? K.bxz : -K.bxz;
-        if (Yc && Z) q += Yc * Z > 0 ? K.byz : -K.byz;
-        const float wi = float(lbq::w(I));
-        Tst = wi * q;
-        float cg = 0.f;
-        if (X) cg += X > 0 ? K.rx : -K.rx;
-        if (Yc) cg += Yc > 0 ? K.ry : -K.ry;
-        if (Z) cg += Z > 0 ? K.rz : -K.rz;
-        cgw = wi * float(lbq::inv_len(I)) * cg;
-    }
-    const float Yst = float(__builtin_fma(K.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
+    float Tst, cgw;
+    link_value<float, I>(L, Tst, cgw);
+    const float Yst = float(__builtin_fma(L.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
     float fT, fY;
     feq_TY<I>(P, rY, rB, vx, vy, vz, fT, fY);
     const unsigned wd = (unsigned)encode_dev<ST, I>(Tst - fT) | ((unsigned)encode_dev<ST, I>(Yst - fY) << 16);
@@ -148,8 +182,9 @@ __device__ __forceinline__ void store_all_dev(const DevParams &P, const OutCoef<
                                               float vx, float vy, float vz, gchar *base, unsigned long long pstride,
                                               unsigned cellb)
 {
+    const LinkSums<float> L = link_sums(K);
     [&]<int... I>(std::integer_sequence<int, I...>) {
-        ((store_one_dev<ST, I>(P, K, rY, rB, vx, vy, vz, base + (unsigned long long)I * pstride, cellb)), ...);
+        ((store_one_dev<ST, I>(P, L, rY, rB, vx, vy, vz, base + (unsigned long long)I * pstride, cellb)), ...);
     }(std::make_integer_sequence<int, lbq::Q>{});
 }
 
@@ -175,7 +210,7 @@ __device__ __forceinline__ CellState<R> cell_state(const DevParams &P, const Mom
     const R drho = R(M.dm[0]), rY = R(M.dm[1]);
     const R rho = R(rho_d);
     const R rB = R(rho_d - M.dm[1]);
-    const R irho = R(1) / rho;
+    const R irho = rcp_of(rho);
     const R ux = M.m[2] * irho, uy = M.m[3] * irho, uz = M.m[4] * irho;
     C.j[0] = M.m[2];
     C.j[1] = M.m[3];
@@ -195,14 +230,14 @@ __device__ __forceinline__ CellState<R> cell_state(const DevParams &P, const Mom
     const R Yxy = M.m[14] - rY * ux * uy;
     const R Yxz = M.m[15] - rY * ux * uz;
     const R Yyz = M.m[16] - rY * uy * uz;
-    const R S = sqrt(Yxx * Yxx + Yyy * Yyy + Yzz * Yzz + R(2) * (Yxy * Yxy + Yxz * Yxz + Yyz * Yyz));
+    const R S = sqrt_of(Yxx * Yxx + Yyy * Yyy + Yzz * Yzz + R(2) * (Yxy * Yxy + Yxz * Yxz + Yyz * Yyz));
     // local relaxation time: ink from its strain rate, air Newtonian, mixed
     // harmonically in the viscosity (Eq. (tauinter))
     const R tauY = tau_ink<R>(P, S, rY);
     const R nuY = cs2 * (tauY - R(0.5)), nuB = cs2 * (R(P.tau_b) - R(0.5));
-    const R inv_nu = (rY * irho) / nuY + (rB * irho) / nuB;
-    const R tau = R(0.5) + R(3) / inv_nu;
-    C.om = R(1) - R(1) / tau;
+    const R inv_nu = (rY * irho) * rcp_of(nuY) + (rB * irho) * rcp_of(nuB);
+    const R tau = R(0.5) + R(3) * rcp_of(inv_nu);
+    C.om = R(1) - rcp_of(tau);
     return C;
 }
 
@@ -220,7 +255,7 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
     const R drho = R(C.drho), rY = R(C.rY);
     const R rho = R(rho_d);
     const R rB = R(rho_d - C.rY);
-    const R irho = R(1) / rho;
+    const R irho = rcp_of(rho);
     const R ux = C.j[0] * irho, uy = C.j[1] * irho, uz = C.j[2] * irho;
 
     // force: body force and the substrate drag (exact-difference method)
@@ -245,15 +280,15 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
     // operator (proportional to |grad rho^N| ~ |F_cg|) is negligible
     const R Fmax = fmax(fabs(Fcx), fmax(fabs(Fcy), fabs(Fcz)));
     const bool pert = Fmax > R(1e-30);
-    const R iF = pert ? R(1) / Fmax : R(0);
+    const R iF = pert ? rcp_of(Fmax) : R(0);
     Fcx *= iF;
     Fcy *= iF;
     Fcz *= iF;
-    const R invFF = pert ? R(1) / (Fcx * Fcx + Fcy * Fcy + Fcz * Fcz) : R(0);
+    const R invFF = pert ? rcp_of(Fcx * Fcx + Fcy * Fcy + Fcz * Fcz) : R(0);
     const R gn2 = G.g[0] * G.g[0] + G.g[1] * G.g[1] + G.g[2] * G.g[2];
-    const R pA = pert ? R(0.5) * R(P.A) * sqrt(gn2) : R(0);
+    const R pA = pert ? R(0.5) * R(P.A) * sqrt_of(gn2) : R(0);
     const R geps2 = gn2 + R(P.eps2);
-    const R inv_geps = geps2 > R(0) ? R(1) / sqrt(geps2) : R(0);
+    const R inv_geps = geps2 > R(0) ? rsqrt_of(geps2) : R(0);
     const R pn = pA * invFF;
 
     OutCoef<R> K;

@@ -569,6 +569,43 @@ __device__ __forceinline__ void pull_bulk_issue_words(gcchar *base, unsigned lon
     }
 }
 
+
+// Reciprocal and square roots.  FP32 takes the hardware approximations
+// (v_rcp_f32, v_sqrt_f32, v_rsq_f32: about 1 ulp, flushed denormal
+// results) where IEEE division would cost a ten-instruction sequence; the
+// operands here are O(1) or clamped away from the denormal range.  FP64 keeps
+// the correctly rounded forms.
+template <typename R>
+__device__ __forceinline__ R rcp_of(R v)
+{
+    return R(1) / v;
+}
+template <>
+__device__ __forceinline__ float rcp_of<float>(float v)
+{
+    return __builtin_amdgcn_rcpf(v);
+}
+template <typename R>
+__device__ __forceinline__ R sqrt_of(R v)
+{
+    return sqrt(v);
+}
+template <>
+__device__ __forceinline__ float sqrt_of<float>(float v)
+{
+    return __builtin_amdgcn_sqrtf(v);
+}
+template <typename R>
+__device__ __forceinline__ R rsqrt_of(R v)
+{
+    return R(1) / sqrt(v);
+}
+template <>
+__device__ __forceinline__ float rsqrt_of<float>(float v)
+{
+    return __builtin_amdgcn_rsqf(v);
+}
+
 // Colour fields of a site from its densities: rho^N (the standard phase field
 // (rho_Y/rho_Y^0 - rho_B/rho_B^0) / (rho_Y/rho_Y^0 + rho_B/rho_B^0)) and the
 // colour fractions.  Zero where the densities vanish.
@@ -577,8 +614,8 @@ __device__ __forceinline__ void chi_of(const DevParams &P, R rY, R rB, R &cN, R 
 {
     R a = rY * R(1.0 / P.rho0[0]), b = rB * R(1.0 / P.rho0[1]);
     R s = a + b, t = rY + rB;
-    const R is = s != R(0) ? R(1) / s : R(0);
-    const R it = t != R(0) ? R(1) / t : R(0);
+    const R is = s != R(0) ? rcp_of(s) : R(0);
+    const R it = t != R(0) ? rcp_of(t) : R(0);
     cN = (a - b) * is;
     cY = rY * it;
     cB = rB * it;
@@ -602,7 +639,7 @@ __device__ __forceinline__ double lg2<double>(double v) { return log2(v); }
 template <typename R>
 __device__ __forceinline__ R ex2(R v);
 template <>
-__device__ __forceinline__ float ex2<float>(float v) { return exp2f(v); }
+__device__ __forceinline__ float ex2<float>(float v) { return __builtin_amdgcn_exp2f(v); }
 template <>
 __device__ __forceinline__ double ex2<double>(double v) { return exp2(v); }
 
@@ -611,7 +648,7 @@ __device__ __forceinline__ R tau_ink(const DevParams &P, R S, R rY)
 {
     if (P.rheology == RHEO_NEWTON) return R(P.tau_y);
     R r = rY > R(P.rho_eps) ? rY : R(P.rho_eps);
-    R s = S * R(3) / r;
+    R s = S * R(3) * rcp_of(r);
     const R tmin = R(P.tau_min), tmax = R(P.tau_max);
     if (P.rheology == RHEO_POWER) {
         if (!(s > R(P.s_lo))) return tmax;
@@ -619,7 +656,7 @@ __device__ __forceinline__ R tau_ink(const DevParams &P, R S, R rY)
         const R n = R(P.n), Kp = R(P.Kp);
         const R ls = lg2<R>(s);
         // start: the smaller of the inertial and the viscous limits, clipped
-        R x = fmin(ls + R(1), (ls - lg2<R>(Kp)) / n);
+        R x = fmin(ls + R(1), (ls - lg2<R>(Kp)) * rcp_of(n));
         x = fmin(fmax(x, R(P.lg_lo)), R(P.lg_hi));
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
@@ -627,7 +664,7 @@ __device__ __forceinline__ R tau_ink(const DevParams &P, R S, R rY)
             R b = Kp * ex2<R>(n * x);
             R G = a + b;
             R h = lg2<R>(G) - ls;
-            x -= h * G / (a + n * b);
+            x -= h * G * rcp_of(a + n * b);
         }
         R tau = R(0.5) + Kp * ex2<R>((n - R(1)) * x);
         return fmin(fmax(tau, tmin), tmax);
@@ -643,17 +680,18 @@ __device__ __forceinline__ R tau_ink(const DevParams &P, R S, R rY)
 #pragma unroll 1
     for (int it = 0; it < 12; ++it) {
         R q = lam > R(0) ? ex2<R>(m * (llam + x)) : R(0);
-        R nu = nuinf + dnu / (R(1) + q);
+        const R iq = rcp_of(R(1) + q);
+        R nu = nuinf + dnu * iq;
         R tau = R(0.5) + nu;
         R h = x + lg2<R>(tau) - ls;
         if (h > R(0)) hi = x; else lo = x;
-        R dnudx = -dnu * m * q / ((R(1) + q) * (R(1) + q));  // d nu / d log2(gdot) * ln 2 folded below
-        R hp = R(1) + dnudx / tau;
-        R xn = x - h / hp;
+        R dnudx = -dnu * m * q * (iq * iq);  // d nu / d log2(gdot) * ln 2 folded below
+        R hp = R(1) + dnudx * rcp_of(tau);
+        R xn = x - h * rcp_of(hp);
         x = (xn > lo && xn < hi) ? xn : R(0.5) * (lo + hi);
     }
     R q = lam > R(0) ? ex2<R>(m * (llam + x)) : R(0);
-    R tau = R(0.5) + nuinf + dnu / (R(1) + q);
+    R tau = R(0.5) + nuinf + dnu * rcp_of(R(1) + q);
     return fmin(fmax(tau, tmin), tmax);
 }
 

@@ -368,14 +368,14 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeo
 // tile rows, the two ring rows, the two ring columns as above): they pull and
 // reduce plane p, keeping the loads of plane p + 1 in flight meanwhile (FP32),
 // and write the colour fields and the tile cells' raw moments to LDS.
-// Waves TY + 3 .. 2 TY + 2 are colliders, one per tile row: in the same
+// The following TY / CR waves are colliders, CR tile rows each: in the same
 // iteration they take plane p - 2 (stencil planes p - 3 .. p - 1, all reduced
 // in earlier iterations) from its moments to its 38 stored values, the local
 // relaxation time included.  One barrier per
 // plane.  Loads and stores are issued by different waves, so neither waits
 // behind the other in a wave's queue of outstanding memory operations.
-template <typename R, int TY, bool FIRST, int ST = ST_PLAIN>
-__global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, StepGeom *__restrict__ G,
+template <typename R, int TY, bool FIRST, int ST = ST_PLAIN, int CR = 1>
+__global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevParams P, StepGeom *__restrict__ G,
                                                                   FusedGrid FG, const void *__restrict__ src,
                                                                   void *__restrict__ dst,
                                                                   const double *__restrict__ momd,
@@ -419,19 +419,22 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
     const unsigned long long pstride = (unsigned long long)N * sizeof(E);
 
     if (wave >= TY + 3) {
-        // ---------------- collider: tile row wave - TY - 3
-        const int r = wave - (TY + 3);
-        const int cx = x0 + lane, cy = y0 + r;
-        const bool tile = cx < P.nx && cy < P.ny;
-        const int xw = wrap_any(cx, P.nx), yw = wrap_any(cy, P.ny);
-        const int row = r + 1, col = lane + 1;
-        const int ii = r * 64 + lane;
-        const long long col_off = (long long)yw * P.nx + xw;
+        // ---------------- collider: tile rows r0, r0 + TY / CR, ... (CR rows)
+        const int r0 = wave - (TY + 3);
         // every wave of the block passes the same barriers: one after the
         // loaders' prologue, then one per plane
         __syncthreads();
         for (int p = z0 - 1; p <= z1 + 1; ++p) {
             const int c = p - 2;
+#pragma unroll 1
+            for (int k = 0; k < CR; ++k) {
+            const int r = r0 + k * (TY / CR);
+            const int cx = x0 + lane, cy = y0 + r;
+            const bool tile = cx < P.nx && cy < P.ny;
+            const int xw = wrap_any(cx, P.nx), yw = wrap_any(cy, P.ny);
+            const int row = r + 1, col = lane + 1;
+            const int ii = r * 64 + lane;
+            const long long col_off = (long long)yw * P.nx + xw;
             if (tile && c >= z0 && st_ok[c & 3][ii]) {
                 const int ss = c & 3;
                 const int sm = (c + 3) & 3, s0 = c & 3, sp1 = (c + 1) & 3;
@@ -478,6 +481,7 @@ __global__ __launch_bounds__((2 * TY + 3) * 64, 1) void k_fused_pc(DevParams P, 
                     mac_next[3 * N + ccell] = u[1];
                     mac_next[4 * N + ccell] = u[2];
                 }
+            }
             }
             __syncthreads();
         }

@@ -541,6 +541,11 @@ bool reduced(int storage) { return storage == LB_BF16_DEV || storage == LB_F16_D
 // 4 x 3 x 66 (TY + 2) values, state ring 2 x 64 TY x (2 FP64 + 10 values).
 constexpr int TY_F32 = 4;
 constexpr int TY_F64 = 5;
+// the producer/consumer step kernel: tile height and tile rows per collider
+// wave, per storage form (FP32 plain; reduced storage, whose moment ring
+// needs LDS)
+constexpr int PC_TY_PLAIN = 4, PC_CR_PLAIN = 1;
+constexpr int PC_TY_DEV = 4, PC_CR_DEV = 1;
 
 FusedGrid fused_grid(const lb_params &p, int ty)
 {
@@ -568,7 +573,7 @@ Layout layout_of(const lb_params &p)
     long long N = (long long)p.nx * p.ny * p.nz;
     size_t rs = real_size(p.storage);
     L.nbm = (N + TPB - 1) / TPB;
-    L.ty = p.storage == LB_F64 ? TY_F64 : TY_F32;
+    L.ty = p.storage == LB_F64 ? TY_F64 : (reduced(p.storage) ? PC_TY_DEV : PC_TY_PLAIN);
     L.fg = fused_grid(p, L.ty);
     {
         // the head box spans at most 2 (r_out + 2) + 4 columns each way
@@ -890,20 +895,20 @@ lb_status timing_mark(lb_handle *h, int k)
 template <typename R, int ST>
 lb_status launch_fused(lb_handle *h)
 {
-    constexpr int TY = sizeof(R) == 8 ? TY_F64 : TY_F32;
+    constexpr int TY = sizeof(R) == 8 ? TY_F64 : (ST == ST_PLAIN ? PC_TY_PLAIN : PC_TY_DEV);
+    constexpr int CR = ST == ST_PLAIN ? PC_CR_PLAIN : PC_CR_DEV;
     const Layout &L = h->L;
     void *src = pops_at(h, h->cur), *dst = pops_at(h, 1 - h->cur);
     if constexpr (sizeof(R) == 4) {
+        const dim3 block((TY + 3 + TY / CR) * 64);
         if (h->first)
-            hipLaunchKernelGGL((k_fused_pc<R, TY, true, ST>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
-                               h->stream, h->P, geo(h), L.fg, src, dst, as<double>(h, L.momd), as<R>(h, L.mom),
-                               as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t), mo_at(h, h->cur),
-                               mo_at(h, 1 - h->cur));
+            hipLaunchKernelGGL((k_fused_pc<R, TY, true, ST, CR>), dim3((unsigned)L.nbf), block, 0, h->stream, h->P,
+                               geo(h), L.fg, src, dst, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                               as<R>(h, L.ghost), mac_at<R>(h, h->t), mo_at(h, h->cur), mo_at(h, 1 - h->cur));
         else
-            hipLaunchKernelGGL((k_fused_pc<R, TY, false, ST>), dim3((unsigned)L.nbf), dim3((2 * TY + 3) * 64), 0,
-                               h->stream, h->P, geo(h), L.fg, src, dst, as<double>(h, L.momd), as<R>(h, L.mom),
-                               as<R>(h, L.chi), as<R>(h, L.ghost), mac_at<R>(h, h->t), mo_at(h, h->cur),
-                               mo_at(h, 1 - h->cur));
+            hipLaunchKernelGGL((k_fused_pc<R, TY, false, ST, CR>), dim3((unsigned)L.nbf), block, 0, h->stream, h->P,
+                               geo(h), L.fg, src, dst, as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
+                               as<R>(h, L.ghost), mac_at<R>(h, h->t), mo_at(h, h->cur), mo_at(h, 1 - h->cur));
     } else {
         static_assert(ST == ST_PLAIN, "FP64 storage is plain");
         const R *s64 = reinterpret_cast<const R *>(src);
