@@ -46,6 +46,7 @@ struct DevParams {
     int periodic_z;
     int face_lo, face_hi;
     long long N;
+    long long NP;              // population plane stride, in stored elements (N plus padding)
     double rho_ref;            // shift of set 0 (air reference density)
     double rho0[2];            // phase-field normalisation
     double phi[2][3];          // phi_i^k per shell
@@ -265,7 +266,7 @@ struct PopSrc {
     static_assert(sizeof(R) == 4, "reduced storage computes in FP32");
     const unsigned *s;
     const float *mo;  // NMO x N source moments
-    long long N;
+    long long N, NP;  // cells; population plane stride
     // what a link needs from memory: the packed word of population plane
     // `plane` at `cell` and that cell's moments; decoded for link I
     struct Raw {
@@ -275,7 +276,7 @@ struct PopSrc {
     __device__ __forceinline__ Raw load_raw(int plane, long long cell) const
     {
         Raw r;
-        r.w = s[plane * N + cell];
+        r.w = s[plane * NP + cell];
 #pragma unroll
         for (int k = 0; k < NMO; ++k) r.m[k] = mo[k * N + cell];
         return r;
@@ -298,13 +299,13 @@ struct PopSrc {
 template <typename R>
 struct PopSrc<R, ST_PLAIN> {
     const R *s;
-    long long N;
+    long long N, NP;  // cells; population plane stride
     struct Raw {
         R T, Y;
     };
     __device__ __forceinline__ Raw load_raw(int plane, long long cell) const
     {
-        return Raw{s[plane * N + cell], s[(lbq::Q + plane) * N + cell]};
+        return Raw{s[plane * NP + cell], s[(lbq::Q + plane) * NP + cell]};
     }
     template <int I>
     __device__ __forceinline__ void finish(const DevParams &, const Raw &r, R &T, R &Y) const
@@ -315,8 +316,8 @@ struct PopSrc<R, ST_PLAIN> {
     template <int I>
     __device__ __forceinline__ void get(const DevParams &, long long cell, R &T, R &Y) const
     {
-        T = s[I * N + cell];
-        Y = s[(lbq::Q + I) * N + cell];
+        T = s[I * NP + cell];
+        Y = s[(lbq::Q + I) * NP + cell];
     }
 };
 

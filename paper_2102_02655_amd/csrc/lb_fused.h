@@ -235,7 +235,7 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeo
     const bool head_col = active && in_box(P, Box3{head.x0, head.y0, 0, head.w, head.h, P.nz}, xw, yw, 0);
     const long long col_off = (long long)yw * P.nx + xw;
     const long long plane_sz = (long long)P.nx * P.ny;
-    const unsigned long long pstride = (unsigned long long)N * sizeof(R);  // bytes per population plane
+    const unsigned long long pstride = (unsigned long long)P.NP * sizeof(R);  // bytes per population plane
     bool ok1 = false, ok2 = false;  // plane p-1 / p-2 of this tile cell is fluid
 
     for (int p = z0 - 1; p <= z1 + 1; ++p) {
@@ -416,7 +416,7 @@ __global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevPara
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long N = P.N;
     const long long plane_sz = (long long)P.nx * P.ny;
-    const unsigned long long pstride = (unsigned long long)N * sizeof(E);
+    const unsigned long long pstride = (unsigned long long)P.NP * sizeof(E);
 
     if (wave >= TY + 3) {
         // ---------------- collider: tile rows r0, r0 + TY / CR, ... (CR rows)
