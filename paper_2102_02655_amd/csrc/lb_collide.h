@@ -319,12 +319,12 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
         store_all<R>(P, K, fresh_global(dst), fresh_uniform(pstride), cellb);
     } else {
         store_all_dev<ST>(P, K, rY, rB, vx, vy, vz, fresh_global(dst), fresh_uniform(pstride), cellb);
-        const long long N = P.N;
+        const long long NM = P.NM;
         mo_dst[cell] = rY;
-        mo_dst[N + cell] = rB;
-        mo_dst[2 * N + cell] = vx;
-        mo_dst[3 * N + cell] = vy;
-        mo_dst[4 * N + cell] = vz;
+        mo_dst[NM + cell] = rB;
+        mo_dst[2 * NM + cell] = vx;
+        mo_dst[3 * NM + cell] = vy;
+        mo_dst[4 * NM + cell] = vz;
     }
     out_rY = rY;
     out_rB = rB;

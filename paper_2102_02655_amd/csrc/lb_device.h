@@ -47,6 +47,7 @@ struct DevParams {
     int face_lo, face_hi;
     long long N;
     long long NP;              // population plane stride, in stored elements (N plus padding)
+    long long NM;              // source-moment plane stride of the reduced forms (floats)
     double rho_ref;            // shift of set 0 (air reference density)
     double rho0[2];            // phase-field normalisation
     double phi[2][3];          // phi_i^k per shell
@@ -265,8 +266,8 @@ template <typename R, int ST>
 struct PopSrc {
     static_assert(sizeof(R) == 4, "reduced storage computes in FP32");
     const unsigned *s;
-    const float *mo;  // NMO x N source moments
-    long long N, NP;  // cells; population plane stride
+    const float *mo;      // NMO planes of source moments
+    long long N, NP, NM;  // cells; population and moment plane strides
     // what a link needs from memory: the packed word of population plane
     // `plane` at `cell` and that cell's moments; decoded for link I
     struct Raw {
@@ -278,7 +279,7 @@ struct PopSrc {
         Raw r;
         r.w = s[plane * NP + cell];
 #pragma unroll
-        for (int k = 0; k < NMO; ++k) r.m[k] = mo[k * N + cell];
+        for (int k = 0; k < NMO; ++k) r.m[k] = mo[k * NM + cell];
         return r;
     }
     template <int I>

@@ -587,7 +587,7 @@ __global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevPara
                     const int mx = wrap_any(x0 - 2 + k % MW, P.nx), my = wrap_any(y0 - 2 + k / MW, P.ny);
                     const long long mc = (long long)zq * plane_sz + (long long)my * P.nx + mx;
 #pragma unroll
-                    for (int m = 0; m < NMO; ++m) mreg[r][m] = mo_src[m * N + mc];
+                    for (int m = 0; m < NMO; ++m) mreg[r][m] = mo_src[m * P.NM + mc];
                 }
             }
         }

@@ -119,7 +119,7 @@ __global__ __launch_bounds__(TPB) void k_init(DevParams P, const StepGeom *__res
         unsigned *d = reinterpret_cast<unsigned *>(dst_v);
         for (int i = 0; i < lbq::Q; ++i) d[i * P.NP + cell] = 0;
         const double m[NMO] = {rY, rB, ux, uy, uz};
-        for (int k = 0; k < NMO; ++k) mo[k * P.N + cell] = solid ? 0.f : float(m[k]);
+        for (int k = 0; k < NMO; ++k) mo[k * P.NM + cell] = solid ? 0.f : float(m[k]);
         return;
     }
     R *dT = reinterpret_cast<R *>(dst_v), *dY = dT + (long long)lbq::Q * P.NP;
@@ -543,6 +543,7 @@ bool reduced(int storage) { return storage == LB_BF16_DEV || storage == LB_F16_D
 // wave reads or writes together -- on the same memory channels; planes of
 // 16 MiB and more are therefore spaced by one MiB and 256 B of padding
 // (measured: about 4% less time per step on the 512 x 256 x 128 print bed).
+// The reduced forms' five source-moment planes are spaced the same way.
 long long plane_stride(long long N, int storage)
 {
     const long long esz = reduced(storage) ? 4 : (long long)pop_size(storage);
@@ -607,7 +608,7 @@ Layout layout_of(const lb_params &p)
     L.pops = off;
     off += 2 * al(pop_set_bytes(N, p.storage));
     L.dmo = off;  // source moments of the reduced storage forms (two copies)
-    if (reduced(p.storage)) off += 2 * al(NMO * (size_t)N * 4);
+    if (reduced(p.storage)) off += 2 * al(NMO * (size_t)plane_stride(N, LB_F32) * 4);
     L.momd = off;
     off += al(2 * (size_t)N * 8);
     L.mom = off;
@@ -673,6 +674,7 @@ DevParams make_dev(const lb_params &p)
     P.nz = p.nz;
     P.N = (long long)p.nx * p.ny * p.nz;
     P.NP = plane_stride(P.N, p.storage);
+    P.NM = plane_stride(P.N, LB_F32);
     P.periodic_z = p.face_zlo == LB_FACE_PERIODIC;
     P.face_lo = p.face_zlo;
     P.face_hi = p.face_zhi;
@@ -819,7 +821,7 @@ char *pops_at(lb_handle *h, int which)
 float *mo_at(lb_handle *h, int which)
 {
     if (!reduced(h->p.storage)) return nullptr;
-    return as<float>(h, h->L.dmo + which * al(NMO * (size_t)h->P.N * 4));
+    return as<float>(h, h->L.dmo + which * al(NMO * (size_t)h->P.NM * 4));
 }
 
 template <typename R, int ST>
@@ -831,6 +833,7 @@ PopSrc<R, ST> pop_src(lb_handle *h, int which)
     } else {
         s.s = reinterpret_cast<const unsigned *>(pops_at(h, which));
         s.mo = mo_at(h, which);
+        s.NM = h->P.NM;
     }
     s.N = h->P.N;
     s.NP = h->P.NP;

@@ -79,3 +79,34 @@ def test_reduced_storage_nozzle_extrusion_1000_steps(storage):
     print(f"{storage} extrusion 1000 steps: rho_Y {errs[0]:.2e} rho_B {errs[1]:.2e} u {errs[2]:.2e}")
     for e, b in zip(errs, BOUND[storage]):
         assert e <= b, (errs, BOUND[storage])
+
+
+@pytest.fixture(scope="module")
+def print_bed_oracle():
+    from oracle import oracle as O
+
+    cfg = W.print_bed(storage="f64")
+    ry, rb = W.nozzle_fields(cfg)
+    o = O.OracleSim(cfg, ry, rb)
+    o.step(3)
+    out = o.moments()
+    del o
+    return cfg, ry, rb, out
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("storage", ["bf16dev", "f16dev"])
+def test_reduced_storage_print_bed_full_size(print_bed_oracle, storage):
+    """The 512x256x128 print bed (population and moment planes of 64 MiB,
+    spaced by padding): three steps against the oracle over the whole box."""
+    from paper_2102_02655_amd import lbprint as LB
+
+    cfg, ry, rb, ref = print_bed_oracle
+    s = LB.Sim(dict(cfg, storage=storage), ry, rb)
+    s.step(3)
+    g = s.moments(dtype=np.float64)
+    errs = (rel(g[0], ref[0]), rel(g[1], ref[1]), rel(g[2], ref[2]))
+    print(f"{storage} print bed 3 steps: rho_Y {errs[0]:.2e} rho_B {errs[1]:.2e} u {errs[2]:.2e}")
+    for e, b in zip(errs, BOUND[storage]):
+        assert e <= b, (errs, BOUND[storage])
+    s.close()
