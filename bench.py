@@ -103,13 +103,19 @@ def serve(args):
     from paper_2102_02655_amd import lbprint as LB
     from paper_2102_02655_amd import serving as S
 
-    reqs = S.make_requests(count=args.serve_count, seed=4, rate=args.serve_rate, steps=args.serve_steps)
+    st = args.serve_storage
+    reqs = S.make_requests(count=args.serve_count, seed=4, rate=args.serve_rate, steps=args.serve_steps, storage=st)
     log = (lambda m: print(m, file=sys.stderr, flush=True)) if args.verbose else None
     warm = S.make_requests(count=2, seed=99, rate=1000.0, lmin=32, lmax=40, steps=4)
     S.Server(8 << 30, chunk=2).run(warm)  # library load, first captures
     torch.cuda.synchronize()
     batched = S.Server(int(args.serve_budget_gb * 1e9), chunk=args.serve_chunk, keep_fields=False).run(reqs, log=log)
-    seq = S.run_sequential(reqs, log=log)
+    # the baseline is plain FP32 served one request at a time
+    seq = None
+    if not args.serve_skip_sequential:
+        base = reqs if st == "f32" else S.make_requests(count=args.serve_count, seed=4, rate=args.serve_rate,
+                                                        steps=args.serve_steps, storage="f32")
+        seq = S.run_sequential(base, log=log)
     # spot check: a few requests rerun alone reproduce the served masses bit for bit
     same = True
     by_id = {r.id: r for r in batched.results}
@@ -119,7 +125,7 @@ def serve(args):
         _, _, _, cons = sim.moments(dtype=np.float64)
         same &= bool(np.array_equal(cons["mass"], by_id[req.id].mass))
         sim.close()
-    b, q = batched.summary(), seq.summary()
+    b, q = batched.summary(), (seq.summary() if seq is not None else None)
     out = {
         "metric": "sweep sims/hour",
         "value": b["sims_per_hour"],
@@ -131,11 +137,75 @@ def serve(args):
         "data": "synthetic",
         "config": {"workload": f"parameter sweep: {args.serve_count} printing simulations, cubic boxes L~U{{32..160}}, "
                                f"{args.serve_steps} steps each, Poisson arrivals {args.serve_rate}/s",
-                   "budget_GB": args.serve_budget_gb, "chunk": args.serve_chunk},
+                   "storage": st, "budget_GB": args.serve_budget_gb, "chunk": args.serve_chunk},
         "batched": b,
         "sequential": q,
         "mix_equals_alone": same,
     }
+    print(json.dumps(out), flush=True)
+
+
+def largest(args):
+    """The largest single domain, 1024x512x384 (201M cells): footprint, MLUPS,
+    the HBM roofline of the fused kernel and the FP64 mass ledger over the run."""
+    import torch
+
+    from paper_2102_02655_amd import lbprint, workloads as W
+
+    st = args.storage or "bf16dev"
+    cfg = W.largest_domain(storage=st)
+    nx, ny, nz = cfg["shape"]
+    cells = nx * ny * nz
+    ry, rb = W.nozzle_fields(cfg)
+    sim = lbprint.Sim(cfg, ry, rb, device="cuda:0")
+    del ry, rb
+    c0 = sim.moments_device(None, None, None)
+    print(f"largest domain {nx}x{ny}x{nz} {st}: created, footprint {sim.nbytes / 1e9:.2f} GB", file=sys.stderr,
+          flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sim.timing(False)
+    tm = sim.timing_read()
+    c1 = sim.moments_device(None, None, None)
+    mlups = cells * args.steps / dt / 1e6
+    bpl = BYTES_PER_LU[st]
+    k_ms = tm["step_ms"] / max(tm["steps"], 1)
+    achieved = bpl * cells / (k_ms * 1e-3) / 1e9
+    # mass ledger since creation: change = wall + open-face + created - deleted
+    resid = []
+    for k in range(2):
+        lhs = c1["mass"][k] - c0["mass"][k]
+        rhs = c1["mass_wall"][k] + c1["mass_open"][k] + c1["mass_created"][k] - c1["mass_deleted"][k]
+        resid.append(abs(lhs - rhs) / c1["mass"][1])
+    out = {
+        "metric": "MLUPS",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if st == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"largest single domain, D3Q19 {nx}x{ny}x{nz}, moving head u=0.01, r_in 24, "
+                               f"power-law n=0.5", "cells": cells, "storage": st},
+        "footprint_GB": sim.nbytes / 1e9,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_fused_pc", "kernel_ms": k_ms,
+                     "algorithmic_bytes": bpl * cells, "prep_ms": tm["prep_ms"] / max(tm["steps"], 1)},
+        "mass": list(map(float, c1["mass"])),
+        "mass_ledger_residual_rel": resid,
+        "cpu_baseline": None,
+    }
+    sim.close()
     print(json.dumps(out), flush=True)
 
 
@@ -144,7 +214,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "bf16dev", "f16dev"])
+    ap.add_argument("--storage", default=None, choices=["f32", "f64", "bf16dev", "f16dev"],
+                    help="population storage (default: f32 on the print bed, bf16dev on the largest domain)")
+    ap.add_argument("--workload", default="print_bed", choices=["print_bed", "largest"],
+                    help="print_bed: the 512x256x128 benchmark; largest: the 1024x512x384 domain")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", action="store_true", help="first run a plain copy of known size (PMC scaling)")
     ap.add_argument("--serve", action="store_true", help="run the serving sweep instead of the step benchmark")
@@ -153,6 +226,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-chunk", type=int, default=20)
+    ap.add_argument("--serve-storage", default="f32", choices=["f32", "bf16dev", "f16dev"])
+    ap.add_argument("--serve-skip-sequential", action="store_true", help="skip the one-at-a-time FP32 baseline")
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -162,6 +237,11 @@ def main():
     if args.serve:
         serve(args)
         return
+    if args.workload == "largest":
+        largest(args)
+        return
+    if args.storage is None:
+        args.storage = "f32"
 
     import torch
 

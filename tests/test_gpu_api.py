@@ -1,4 +1,4 @@
-"""GPU tests of the host-side API around the step (timing record)."""
+"""GPU tests of the host-side API around the step (timing record, sums-only read-out)."""
 import numpy as np
 import pytest
 
@@ -25,4 +25,21 @@ def test_timing_record_counts_steps():
     assert sim.timing_read()["steps"] == 0  # reading clears
     _, _, _, cons = sim.moments()
     assert np.isfinite(cons["mass"]).all()
+    sim.close()
+
+
+def test_moments_without_fields_gives_the_same_sums():
+    """lb_moments with no field outputs (all three pointers null) still
+    returns the conserved sums, equal to those of a full read-out."""
+    from paper_2102_02655_amd import lbprint
+
+    cfg = W.printing((40, 32, 24), head_x0=(12.0, 15.5), r_in=4.0, tip_z=10.0, head_v=(0.03, 0.011), u_ink=0.02,
+                     n=0.5, storage="bf16dev")
+    ry, rb = W.nozzle_fields(cfg)
+    sim = lbprint.Sim(cfg, ry, rb)
+    sim.step(7)
+    c_none = sim.moments_device(None, None, None)
+    _, _, _, c_full = sim.moments()
+    for key in c_full:
+        assert np.array_equal(c_none[key], c_full[key]), key
     sim.close()
