@@ -33,7 +33,7 @@ namespace {
 
 constexpr int TPB = 256;       // threads per block of the per-cell kernels
 constexpr int NB_SPARSE = 256;  // fixed grid of the head-box kernels (deterministic slots)
-constexpr int NB_PRE = 2048;    // fixed grid of the boundary preparation kernel
+constexpr int NB_PRE = 2048;    // most blocks of the boundary preparation kernel (slots of its sums)
 constexpr int NSLOT = 6;       // per-block FP64 sums: wall Y, wall B, open Y, open B, deleted Y, deleted B
 constexpr int NPART = 6;       // per-block FP64 sums of the output: mass Y, B, momentum xyz, unstable
 
@@ -222,16 +222,32 @@ __global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__
     const int nbox = sg.nbox;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
     int any = 0;
-    for (int bi = 0; bi < nbox; ++bi) {
+    // one index over the cells of all boxes, so that the head box and the
+    // face layers go to different threads and run side by side
+    long long vol[3];
+    long long total = 0;
+    for (int bi = 0; bi < 3; ++bi) {
         const Box3 B = bi == 0 ? b0 : (bi == 1 ? b1 : b2);
-        const long long total = (long long)B.w * B.h * B.d;
-        for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
-            int ix = (int)(k % B.w), iy = (int)((k / B.w) % B.h), iz = (int)(k / ((long long)B.w * B.h));
-            int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
-            if (z < 0 || z >= P.nz) continue;
-            if (bi > 0 && in_box(P, b0, x, y, z)) continue;
-            moments_cell<R>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc, any);
+        vol[bi] = bi < nbox ? (long long)B.w * B.h * B.d : 0;
+        total += vol[bi];
+    }
+    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+        int bi = 0;
+        long long kk = k;
+        if (kk >= vol[0]) {
+            kk -= vol[0];
+            bi = 1;
+            if (kk >= vol[1]) {
+                kk -= vol[1];
+                bi = 2;
+            }
         }
+        const Box3 B = bi == 0 ? b0 : (bi == 1 ? b1 : b2);
+        int ix = (int)(kk % B.w), iy = (int)((kk / B.w) % B.h), iz = (int)(kk / ((long long)B.w * B.h));
+        int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
+        if (z < 0 || z >= P.nz) continue;
+        if (bi > 0 && in_box(P, b0, x, y, z)) continue;
+        moments_cell<R>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc, any);
     }
     if (!__syncthreads_or(any)) return;
     block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, true);
@@ -531,6 +547,8 @@ struct Layout {
     long long nbf;   // its block count
     int ty;          // its tile height
     unsigned nb_wall;  // blocks of the wall-density kernel (grid-stride over the head box)
+    unsigned nb_pre;   // blocks of the boundary preparation kernel (its largest cell count, at most NB_PRE)
+    unsigned nb_create;  // blocks of the node-creation kernel (the head box, at most NB_SPARSE)
 };
 
 size_t real_size(int storage) { return storage == LB_F64 ? 8 : 4; }                    // arithmetic type
@@ -602,6 +620,11 @@ Layout layout_of(const lb_params &p)
         long long bw = std::min<long long>(wmax, p.nx), bh = std::min<long long>(wmax, p.ny);
         long long tot = bw * bh * p.nz;
         L.nb_wall = (unsigned)std::max<long long>(1, std::min<long long>((tot + TPB - 1) / TPB, 4096));
+        // sized to the work, so that the preparation of a small box leaves
+        // the GPU to other simulations' kernels
+        const long long faces = p.face_zlo == LB_FACE_PERIODIC ? 0 : 2LL * p.nx * p.ny;
+        L.nb_pre = (unsigned)std::max<long long>(1, std::min<long long>((tot + faces + TPB - 1) / TPB, NB_PRE));
+        L.nb_create = (unsigned)std::max<long long>(1, std::min<long long>((tot + TPB - 1) / TPB, NB_SPARSE));
     }
     L.nbf = (long long)L.fg.ntx * L.fg.nty * L.fg.nzc;
     size_t off = 0;
@@ -868,7 +891,7 @@ lb_status run_readout(lb_handle *h)
                        as<R>(h, L.chi), as<double>(h, L.pend), h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
-        hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, geo(h),
+        hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
                            as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.pendc), 0);
         if (lb_status s = check_launch(h, "k_create")) return s;
     } else {
@@ -964,14 +987,14 @@ lb_status run_step(lb_handle *h)
     if (!h->p.has_nozzle && h->P.periodic_z)
         if (lb_status s = launch_clock(h)) return s;  // otherwise k_pre computes the geometry
     if (h->p.has_nozzle || !h->P.periodic_z) {
-        hipLaunchKernelGGL((k_pre<R, ST>), dim3(NB_PRE), dim3(TPB), 0, h->stream, h->P, geo(h), pop_src<R, ST>(h, h->cur),
+        hipLaunchKernelGGL((k_pre<R, ST>), dim3(L.nb_pre), dim3(TPB), 0, h->stream, h->P, geo(h), pop_src<R, ST>(h, h->cur),
                            mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi),
                            as<double>(h, L.cumpre), h->first);
         if (lb_status s = check_launch(h, "k_pre")) return s;
     }
     if (h->p.has_nozzle) {
         if (!h->first) {
-            hipLaunchKernelGGL(k_create<R>, dim3(NB_SPARSE), dim3(TPB), 0, h->stream, h->P, geo(h),
+            hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
                                as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.cumc), 1);
             if (lb_status s = check_launch(h, "k_create")) return s;
         }
@@ -1182,7 +1205,9 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     hipError_t e = hipMemcpyAsync(dry, rho_y, N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(drb, rho_b, N * 8, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, 3 * N * 8, hipMemcpyHostToDevice, h->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cumpre, 0, L.pendc - L.cumpre, h->stream);
+    // cumulative and pending per-block sums start at zero (kernels sized to a
+    // box's work leave the slots past their grid untouched)
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cumpre, 0, L.red - L.cumpre, h->stream);
     // device step counter: t = 0, no step taken (the stream is synchronised
     // below, before g0 goes out of scope)
     StepGeom g0;
