@@ -222,32 +222,16 @@ __global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__
     const int nbox = sg.nbox;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
     int any = 0;
-    // one index over the cells of all boxes, so that the head box and the
-    // face layers go to different threads and run side by side
-    long long vol[3];
-    long long total = 0;
-    for (int bi = 0; bi < 3; ++bi) {
+    for (int bi = 0; bi < nbox; ++bi) {
         const Box3 B = bi == 0 ? b0 : (bi == 1 ? b1 : b2);
-        vol[bi] = bi < nbox ? (long long)B.w * B.h * B.d : 0;
-        total += vol[bi];
-    }
-    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
-        int bi = 0;
-        long long kk = k;
-        if (kk >= vol[0]) {
-            kk -= vol[0];
-            bi = 1;
-            if (kk >= vol[1]) {
-                kk -= vol[1];
-                bi = 2;
-            }
+        const long long total = (long long)B.w * B.h * B.d;
+        for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+            int ix = (int)(k % B.w), iy = (int)((k / B.w) % B.h), iz = (int)(k / ((long long)B.w * B.h));
+            int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
+            if (z < 0 || z >= P.nz) continue;
+            if (bi > 0 && in_box(P, b0, x, y, z)) continue;
+            moments_cell<R>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc, any);
         }
-        const Box3 B = bi == 0 ? b0 : (bi == 1 ? b1 : b2);
-        int ix = (int)(kk % B.w), iy = (int)((kk / B.w) % B.h), iz = (int)(kk / ((long long)B.w * B.h));
-        int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
-        if (z < 0 || z >= P.nz) continue;
-        if (bi > 0 && in_box(P, b0, x, y, z)) continue;
-        moments_cell<R>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc, any);
     }
     if (!__syncthreads_or(any)) return;
     block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, true);
