@@ -3,11 +3,11 @@
 Requests (a printing set-up, an initial state, a step count) arrive over
 time.  The server keeps every admitted simulation's state resident on the
 GPU, admits waiting requests in arrival order while their device footprint
-(lb_footprint) fits the memory budget, and advances all admitted simulations
-together: each round is one lb_step_batch call (per simulation one launch of
-its captured chain of steps, each simulation on a stream of its own so their
-work overlaps on the device), after which finished simulations are read out
-and released, so requests that arrive while others run join the batch as
+(lb_footprint) fits the memory budget, and keeps every admitted simulation
+stepping: each has a stream of its own with up to two chunks of steps queued
+(each chunk one launch of its captured chain of steps), so their work
+overlaps on the device; a simulation whose last chunk has completed is read
+out and released at once, and requests that arrive while others run join as
 memory frees up.
 
 The comparison point ("sequential") serves the same trace one request at a
@@ -59,7 +59,7 @@ class RunStats:
     results: list = field(default_factory=list)
     wall: float = 0.0
     peak_bytes: int = 0
-    rounds: int = 0
+    launches: int = 0   # chunk launches (batched) or runs (sequential)
 
     def summary(self) -> dict:
         lat = np.array([r.latency for r in self.results])
@@ -74,7 +74,7 @@ class RunStats:
             "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "latency_mean_s": float(lat.mean()) if len(lat) else None,
             "peak_resident_GB": self.peak_bytes / 1e9,
-            "rounds": self.rounds,
+            "launches": self.launches,
         }
 
 
@@ -92,21 +92,31 @@ def make_requests(count=256, seed=4, rate=4.0, lmin=32, lmax=160, steps=2000, st
 class Server:
     """Continuous batching over one GPU."""
 
-    def __init__(self, budget_bytes: int, chunk: int = 20, device: str = "cuda:0", keep_fields: bool = False):
+    def __init__(self, budget_bytes: int, chunk: int = 20, device: str = "cuda:0", keep_fields: bool = False,
+                 depth: int = 2):
         if chunk < 2:
             raise ValueError("chunk must be >= 2")
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
+        self.depth = int(depth)
         self.device = device
         self.keep_fields = keep_fields
 
     def run(self, requests, log=None) -> RunStats:
+        """Serve `requests` in arrival order.  Every admitted simulation keeps
+        up to `depth` chunks of `chunk` steps queued on its own stream (one
+        lb_step_batch call each, a captured chain of steps); completion is
+        polled per simulation with stream events, so the host never waits for
+        the whole device and the GPU is not left idle while finished
+        simulations are read out or new ones created."""
         import torch
 
         stats = RunStats("batched")
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue = collections.deque()
-        active = []  # [req, sim, steps_left, bytes, admitted_at]
+        active = []  # [req, sim, steps not yet launched, bytes, admitted_at, deque of chunk events]
         used = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
@@ -123,36 +133,48 @@ class Server:
                     break
                 req = queue.popleft()
                 sim = LB.Sim(req.cfg, req.ry, req.rb, device=self.device, stream=torch.cuda.Stream(self.device))
-                active.append([req, sim, req.steps, need, now()])
+                active.append([req, sim, req.steps, need, now(), collections.deque()])
                 used += need
                 stats.peak_bytes = max(stats.peak_bytes, used)
-            if not active:
-                if pending:
-                    wait = pending[0].arrival - now()
-                    if wait > 0:
-                        time.sleep(min(wait, 0.005))
-                continue
-            ks = [min(self.chunk, a[2]) for a in active]
-            LB.step_batch([a[1] for a in active], ks)
-            torch.cuda.synchronize(self.device)
-            stats.rounds += 1
+            progressed = False
             still = []
-            for a, k in zip(active, ks):
-                a[2] -= k
-                if a[2] > 0:
+            for a in active:
+                req, sim, left, need, admitted, inflight = a
+                while inflight and inflight[0].query():
+                    inflight.popleft()
+                    progressed = True
+                while left > 0 and len(inflight) < self.depth:
+                    k = min(self.chunk, left)
+                    LB.step_batch([sim], [k])
+                    ev = torch.cuda.Event()
+                    ev.record(sim.stream)
+                    inflight.append(ev)
+                    left -= k
+                    stats.launches += 1
+                    progressed = True
+                a[2] = left
+                if left > 0 or inflight:
                     still.append(a)
                     continue
-                req, sim = a[0], a[1]
                 ry, rb, u, cons = sim.moments(dtype=np.float64)
                 nx, ny, nz = req.cfg["shape"]
-                res = Result(req.id, req.arrival, a[4], now(), nx * ny * nz, req.steps, cons["mass"],
+                res = Result(req.id, req.arrival, admitted, now(), nx * ny * nz, req.steps, cons["mass"],
                              (ry, rb, u) if self.keep_fields else None)
                 stats.results.append(res)
                 if log:
                     log(f"request {req.id} done: L={nx} latency {res.latency:.3f} s")
                 sim.close()
-                used -= a[3]
+                used -= need
+                progressed = True
             active = still
+            if not progressed:
+                if active:
+                    time.sleep(0.0002)
+                elif pending:
+                    wait = pending[0].arrival - now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.005))
+        torch.cuda.synchronize(self.device)
         stats.wall = now()
         return stats
 
@@ -182,6 +204,6 @@ def run_sequential(requests, device: str = "cuda:0", keep_fields: bool = False, 
         if log:
             log(f"request {req.id} done (sequential): L={nx} latency {res.latency:.3f} s")
         sim.close()
-        stats.rounds += 1
+        stats.launches += 1
     stats.wall = now()
     return stats

@@ -7,11 +7,12 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-def test_server_results_equal_alone_runs():
+@pytest.mark.parametrize("storage", ["f32", "bf16dev"])
+def test_server_results_equal_alone_runs(storage):
     from paper_2102_02655_amd import lbprint as LB
     from paper_2102_02655_amd import serving as S
 
-    reqs = S.make_requests(count=8, seed=11, rate=200.0, lmin=20, lmax=40, steps=30)
+    reqs = S.make_requests(count=8, seed=11, rate=200.0, lmin=20, lmax=40, steps=30, storage=storage)
     budget = sum(LB.footprint(r.cfg) for r in reqs[:3])  # at most ~3 resident at once
     stats = S.Server(budget, chunk=8, keep_fields=True).run(reqs)
     assert sorted(r.id for r in stats.results) == list(range(8))
