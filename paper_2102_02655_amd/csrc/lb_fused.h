@@ -651,16 +651,24 @@ __global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevPara
                 if constexpr (ST == ST_PLAIN) {
                     mom_add_all<R, true>(M, vT, vY);
                 } else {
-                    [&]<int... I>(std::integer_sequence<int, I...>) {
-                        (
-                            [&] {
-                                R T, Y;
-                                decode.template operator()<I>(p, vT[I], vY[I], T, Y);
-                                mom_add<R, I, true>(M, T, Y);
-                                __builtin_amdgcn_sched_barrier(0);
-                            }(),
-                            ...);
-                    }(std::make_integer_sequence<int, lbq::Q>{});
+                    // ring cells need only the two masses (their colour
+                    // fields); the branch is uniform per wave
+                    auto decode_all = [&]<bool FULL>() {
+                        [&]<int... I>(std::integer_sequence<int, I...>) {
+                            (
+                                [&] {
+                                    R T, Y;
+                                    decode.template operator()<I>(p, vT[I], vY[I], T, Y);
+                                    mom_add<R, I, FULL>(M, T, Y);
+                                    __builtin_amdgcn_sched_barrier(0);
+                                }(),
+                                ...);
+                        }(std::make_integer_sequence<int, lbq::Q>{});
+                    };
+                    if (wave < TY)
+                        decode_all.template operator()<true>();
+                    else
+                        decode_all.template operator()<false>();
                 }
                 chi_of<R>(P, R(M.dm[1]), R(P.rho_ref + M.dm[0] - M.dm[1]), cN, cY, cB);
             }
