@@ -56,10 +56,13 @@ typedef enum {
 } lb_status;
 
 /* Population storage.  LB_F64: FP64 storage and arithmetic.  LB_F32: FP32
- * storage and arithmetic (conservation sums always in FP64).  LB_BF16_DEV and
- * LB_F16_DEV (reduced storage: populations kept as 16-bit deviations from the
- * local equilibrium, FP32 arithmetic) are reserved: lb_create rejects them
- * with LB_EINVAL until implemented. */
+ * storage and arithmetic (masses and conservation sums always in FP64).
+ * LB_BF16_DEV and LB_F16_DEV (reduced storage, FP32 arithmetic): each
+ * post-collision population is kept as its deviation from the equilibrium of
+ * its source cell's post-collision moments (Sec. II.A, the modified
+ * equilibrium), in BF16 or as FP16 of deviation / w_i, both colours of a link
+ * packed in one 32-bit word, beside the cell's five moments (rho_Y, rho_B and
+ * the forced velocity) in FP32.  Any other value: LB_EINVAL. */
 typedef enum { LB_F64 = 0, LB_F32 = 1, LB_BF16_DEV = 2, LB_F16_DEV = 3 } lb_storage;
 
 /* Ink rheology (Sec. II.B): constant tau_y; power law nu = K gdot^(n-1); Cross
@@ -116,7 +119,9 @@ typedef struct {
 typedef struct lb_handle lb_handle;
 
 /* Bytes of device workspace a handle needs for these parameters (pure host
- * computation; used for admission).  LB_EINVAL on bad parameters. */
+ * computation; used for admission).  Includes the padding between population
+ * planes (256 B, or 1 MiB + 256 B for planes of 16 MiB and more) and the
+ * full-box auxiliary arrays.  LB_EINVAL on bad parameters. */
 lb_status lb_footprint(const lb_params *p, size_t *bytes);
 
 /* Create a simulation.  rho_y, rho_b: host FP64 [z][y][x] initial densities;
