@@ -146,6 +146,40 @@ __device__ __forceinline__ int classify(const DevParams &P, double hx, double hy
     return ST_FLUID;
 }
 
+// classify() for a site whose column class at the previous head position is
+// already known (cc): the same decision without the geometry.
+__device__ __forceinline__ int classify_cc(const DevParams &P, int cc, int &z, bool near)
+{
+    if (z < 0 || z >= P.nz) {
+        if (P.periodic_z) {
+            z = wrap(z, P.nz);
+        } else {
+            bool lo = z < 0;
+            if (!lo && near) {
+                if (cc == COL_BORE) return ST_LID;
+                if (cc == COL_SHELL) return ST_NOZ;
+            }
+            int face = lo ? P.face_lo : P.face_hi;
+            if (face == FACE_WALL) return lo ? ST_WALL_LO : ST_WALL_HI;
+            return lo ? ST_OPEN_LO : ST_OPEN_HI;
+        }
+    }
+    if (near && P.has_nozzle && (double)z >= P.tip_z && cc == COL_SHELL) return ST_NOZ;
+    return ST_FLUID;
+}
+
+// Column classes of the 3 x 3 columns around (x, y) at the previous head
+// position (cc[1 + dx][1 + dy]); only near the head, where they matter.
+__device__ __forceinline__ void column_classes(const DevParams &P, const HeadPos &H, int x, int y, bool near,
+                                               int (&cc)[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            cc[a][b] = near ? column_class(P, H.hx_p, H.hy_p, wrap(x + a - 1, P.nx), wrap(y + b - 1, P.ny)) : COL_OUT;
+}
+
 __device__ __forceinline__ long long cidx(const DevParams &P, int x, int y, int z)
 {
     return ((long long)z * P.ny + y) * P.nx + x;
@@ -330,8 +364,8 @@ struct PopSrc<R, ST_PLAIN> {
 // pressure faces).  st: the class of x - c_i.
 template <typename R, int I, bool FULL = true>
 __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, const R *__restrict__ mac, int x,
-                                          int y, int z, long long cell, bool near, int st, R Tout, R Yout, Mom<R> &M,
-                                          Flux &fl)
+                                          int y, int z, long long cell, bool near, const int (&cc)[3][3], int st,
+                                          R Tout, R Yout, Mom<R> &M, Flux &fl)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
     const long long N = P.N;
@@ -343,7 +377,7 @@ __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, 
         // u_w = (3 u(x) - u(x + c_i)) / 2 at t-1 when x + c_i was fluid
         R ux = mac[2 * N + cell], uy = mac[3 * N + cell], uz = mac[4 * N + cell];
         int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
-        int s1 = classify(P, H.hx_p, H.hy_p, x1, y1, z1, near);
+        int s1 = classify_cc(P, cc[1 + X][1 + Yc], z1, near);
         if (s1 == ST_FLUID) {
             long long c1 = ((long long)z1 * P.ny + y1) * P.nx + x1;
             ux = (R(3) * ux - mac[2 * N + c1]) * R(0.5);
@@ -384,7 +418,7 @@ __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, 
                 // x, x + c_i, x + 2 c_i (the inward direction), at t-1
                 R r0Y = mac[0 * N + cell], r0B = mac[1 * N + cell];
                 int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
-                int s1 = classify(P, H.hx_p, H.hy_p, x1, y1, z1, near);
+                int s1 = classify_cc(P, cc[1 + X][1 + Yc], z1, near);
                 if (s1 == ST_FLUID) {
                     long long c1 = ((long long)z1 * P.ny + y1) * P.nx + x1;
                     R r1Y = mac[0 * N + c1], r1B = mac[1 * N + c1];
@@ -435,6 +469,8 @@ __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, c
 {
     typename PS::Raw raw[lbq::Q];
     int st[lbq::Q];
+    int cc[3][3];
+    column_classes(P, H, x, y, near && !first, cc);
     [&]<int... I>(std::integer_sequence<int, I...>) {
         (
             [&] {
@@ -445,7 +481,7 @@ __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, c
                     const int xs = X ? wrap(x - X, P.nx) : x;
                     const int ys = Yc ? wrap(y - Yc, P.ny) : y;
                     int zs = z - Z;  // classify wraps it when z is periodic
-                    s_ = (Z == 0 && !near) ? ST_FLUID : classify(P, H.hx_p, H.hy_p, xs, ys, zs, near);
+                    s_ = (Z == 0 && !near) ? ST_FLUID : classify_cc(P, cc[1 - X][1 - Yc], zs, near);
                     const long long scf = ((long long)zs * P.ny + ys) * P.nx + xs;
                     sc = s_ == ST_FLUID ? scf : cell;
                     plane = s_ == ST_FLUID ? I : lbq::opp(I);
@@ -464,7 +500,7 @@ __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, c
                     mom_add<R, I, FULL>(M, T, Y);
                 } else {
                     src.template finish<lbq::opp(I)>(P, raw[I], T, Y);
-                    pull_rule<R, I, FULL>(P, H, mac, x, y, z, cell, near, st[I], T, Y, M, fl);
+                    pull_rule<R, I, FULL>(P, H, mac, x, y, z, cell, near, cc, st[I], T, Y, M, fl);
                 }
             }(),
             ...);
