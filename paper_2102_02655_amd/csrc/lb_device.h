@@ -641,7 +641,9 @@ __device__ __forceinline__ R rsqrt_of(R v)
 template <>
 __device__ __forceinline__ float rsqrt_of<float>(float v)
 {
-    return __builtin_amdgcn_rsqf(v);
+    // a denormal argument is raised to the smallest normal float, so that a
+    // flushed input cannot turn into an infinite result
+    return __builtin_amdgcn_rsqf(fmaxf(v, 1.17549435e-38f));
 }
 
 // Colour fields of a site from its densities: rho^N (the standard phase field
