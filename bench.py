@@ -7,8 +7,12 @@ one full time step of the method on every cell.
 
 Prints one JSON line: whole-step MLUPS, the HBM roofline of the dominant
 kernel (the fused step kernel, timed with HIP events on the library's stream
-over the timed region) and the FP64 CPU oracle timed on a bounded sample of
-the same workload.
+over the timed region; beside it the rate of a plain 1 GiB copy on the same
+GPU) and the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+Other modes: --workload largest (the 1024x512x384 domain, BF16 deviations by
+default) and --serve (the parameter-sweep trace through the continuous-
+batching server and one request at a time).
 """
 from __future__ import annotations
 
@@ -92,6 +96,25 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
     torch.cuda.synchronize()
     print(f"copy probe: {reps} x torch.neg over {nbytes} B (read {nbytes} B + write {nbytes} B per launch)",
           file=sys.stderr, flush=True)
+
+
+def copy_rate(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Attainable HBM rate of a plain elementwise copy (read nbytes, write
+    nbytes per launch), GB/s, timed with events on the current stream."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.neg(a, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def serve(args):
@@ -270,6 +293,7 @@ def main():
     alg_bytes = bpl * cells
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.storage)
+    copy_gbs = copy_rate()
     out = {
         "metric": "MLUPS",
         "value": mlups,
@@ -289,7 +313,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fused_pc", "kernel_ms": k_ms, "algorithmic_bytes": alg_bytes,
                      "prep_ms": tm["prep_ms"] / max(tm["steps"], 1),
-                     "whole_step_GBs": bpl * mlups * 1e6 / 1e9},
+                     "whole_step_GBs": bpl * mlups * 1e6 / 1e9,
+                     # the kernel's algorithmic rate against a plain copy's on this GPU
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "mass": list(map(float, cons["mass"])),
     }
     if not args.no_cpu:
