@@ -167,6 +167,98 @@ def test_power_law_poiseuille(O):
     assert np.linalg.norm(u - ex) / np.linalg.norm(ex) < 5e-3
 
 
+# ------------------------------------------------------- substrate drag
+#
+# Sec. II.B: the friction with the collector is the force -gamma rho_Y u,
+# applied by the exact-difference method where z + 1/2 < drag_range above a
+# z-low wall, relative to the wall's velocity.  Channel of uniform
+# composition c = rho_Y/rho between static walls (z = -1/2 and H - 1/2),
+# body force g.  The drag uses the bare velocity u_b = u - F/(2 rho) (u the
+# physical velocity), so per unit mass F/rho = (g - gamma c u)/(1 - gamma c/2),
+# and the steady momentum balance nu u'' + F/rho = 0 is Brinkman's equation
+#   u'' = k^2 (u - g/(gamma c)),  k^2 = gamma c / (nu (1 - gamma c / 2)),
+# i.e. u = (g/(gamma c)) [1 - cosh(k (z - z_c)) / cosh(k H/2)].
+# The recolouring parameter is set to zero: with beta > 0 a uniform mixture
+# is an unstable fixed point and separates into layers (the model's phase
+# separation), so only beta = 0 keeps c uniform.
+
+def _drag_channel(O, H, g, gamma, drag_range, c_ink, tau=1.0, u_wall=0.0):
+    cfg = W.base_params((1, 1, H), tau_b=tau, tau_y=tau, face_zlo="wall", face_zhi="wall", body_g=(g, 0, 0),
+                        drag_gamma=gamma, drag_range=drag_range, u_zlo=(u_wall, 0, 0), u_zhi=(u_wall, 0, 0),
+                        beta=0.0)
+    s = O.OracleSim(cfg, np.full((H, 1, 1), c_ink), np.full((H, 1, 1), 1.0 - c_ink))
+    return s
+
+
+@pytest.mark.parametrize("c_ink", [1.0, 0.6])
+def test_drag_brinkman_channel(O, c_ink):
+    """Drag over the whole channel: Brinkman's profile.  At c = 0.6 the drag
+    per unit mass is 0.6 gamma (the rho_Y factor); pure air feels none."""
+    H, g, gamma, tau = 32, 1e-6, 1e-2, 1.0
+    s = _drag_channel(O, H, g, gamma, H + 1.0, c_ink, tau)
+    u = _run_to_steady(s, 2000, 50, 1e-13)
+    nu = CS2 * (tau - 0.5)
+    gc = gamma * c_ink
+    k = np.sqrt(gc / (nu * (1 - gc / 2)))
+    z = np.arange(H)
+    ex = g / gc * (1 - np.cosh(k * (z - (H - 1) / 2)) / np.cosh(k * H / 2))
+    assert np.linalg.norm(u - ex) / np.linalg.norm(ex) < 2.5e-3
+    ry, rb, _, _ = s.moments()
+    assert np.abs(ry / (ry + rb) - c_ink).max() < 1e-13  # the composition stays uniform
+
+
+def test_drag_pure_air_is_poiseuille(O):
+    H, g, tau = 32, 1e-6, 1.0
+    s = _drag_channel(O, H, g, 5e-2, H + 1.0, 0.0, tau)
+    u = _run_to_steady(s, 5000, 40, 1e-12)
+    z = np.arange(H)
+    ex = g / (2 * CS2 * (tau - 0.5)) * (z + 0.5) * (H - 0.5 - z)
+    assert np.linalg.norm(u - ex) / np.linalg.norm(ex) < 1e-3
+
+
+def test_drag_is_relative_to_the_moving_substrate(O):
+    """Both walls moving at U, drag everywhere, no body force: the uniform
+    flow at U is the steady state (the drag acts on u - u_wall)."""
+    H, U = 16, 0.01
+    s = _drag_channel(O, H, 0.0, 5e-2, H + 1.0, 0.7, 0.8, u_wall=U)
+    s.step(3000)
+    u = s.moments()[2][:, 0, 0, 0]
+    assert np.abs(u - U).max() < 1e-12
+
+
+def _drag_layer_profile(H, g, gamma, R, nu):
+    """Drag on the cells z = 0 .. R-1 (the continuum layer -1/2 < z < R - 1/2),
+    none above: Brinkman below z_m = R - 1/2, Poiseuille above, u and the
+    shear stress nu u' continuous at z_m, u = 0 on both walls."""
+    k = np.sqrt(gamma / (nu * (1 - gamma / 2)))
+    zm = R - 0.5
+    sm, L = zm + 0.5, H - 0.5 - zm
+    ui = g / gamma
+    # lower: u = ui (1 - cosh(k s)) + b sinh(k s), s = z + 1/2; upper:
+    # u = -g/(2 nu) (z - zm)^2 + C (z - zm) + D with D = u(zm), C = u'(zm)
+    a0 = ui * (1 - np.cosh(k * sm)) - ui * k * np.sinh(k * sm) * L - g / (2 * nu) * L * L
+    b = -a0 / (np.sinh(k * sm) + k * np.cosh(k * sm) * L)
+    D = ui * (1 - np.cosh(k * sm)) + b * np.sinh(k * sm)
+    Cc = -ui * k * np.sinh(k * sm) + b * k * np.cosh(k * sm)
+    z = np.arange(H, dtype=float)
+    low = ui * (1 - np.cosh(k * (z + 0.5))) + b * np.sinh(k * (z + 0.5))
+    up = -g / (2 * nu) * (z - zm) ** 2 + Cc * (z - zm) + D
+    return np.where(z < zm, low, up)
+
+
+def test_drag_acts_within_its_range_only(O):
+    """drag_range = 4: the cells z = 0..3 (z + 1/2 < 4) feel the drag.  The
+    composite profile is matched to 1.5e-2 (the coefficient jumps within a
+    cell); a range of 3 or 5 cells is 8-11% away."""
+    H, g, gamma, tau = 32, 1e-6, 5e-2, 1.0
+    s = _drag_channel(O, H, g, gamma, 4.0, 1.0, tau)
+    u = _run_to_steady(s, 2000, 60, 1e-13)
+    nu = CS2 * (tau - 0.5)
+    err = {R: np.linalg.norm(u - _drag_layer_profile(H, g, gamma, R, nu)) /
+           np.linalg.norm(_drag_layer_profile(H, g, gamma, R, nu)) for R in (3, 4, 5)}
+    assert err[4] < 1.5e-2 and err[3] > 5e-2 and err[5] > 5e-2, err
+
+
 # ---------------------------------------------------------------- inlet
 
 def test_inlet_lid_mass_flux(O):
@@ -250,6 +342,55 @@ def test_moving_head_creation_and_mass_balance(O):
             # an equilibrium of its own density moving with the head (phi = w at alpha = 1/3)
             feq = f.sum() * w * (1 + cu / CS2 + cu ** 2 / (2 * CS2 ** 2) - U @ U / (2 * CS2))
             assert np.allclose(f, feq, rtol=1e-13, atol=1e-16)
+    _check_created_densities(s, created, solid_before, v)
+
+
+def _check_created_densities(s, created, solid_before, v):
+    """A created node's density per colour is the mean over its lattice
+    neighbours that are fluid both before and after the move (Sec. II.B),
+    read from the fields after the step; its velocity is the head's."""
+    ry, rb, u, _ = s.moments()
+    nz, ny, nx = ry.shape
+    solid_after = s.solid()
+    c = s.velocities()
+    for (z, y, x) in zip(*np.nonzero(created)):
+        vals = []
+        for ci in c[1:]:
+            zz = z + ci[2]
+            if not 0 <= zz < nz:
+                continue
+            yy, xx = (y + ci[1]) % ny, (x + ci[0]) % nx
+            if solid_before[zz, yy, xx] or solid_after[zz, yy, xx]:
+                continue
+            vals.append((ry[zz, yy, xx], rb[zz, yy, xx]))
+        assert vals, "a released node next to the shell always has fluid neighbours"
+        mean = np.mean(np.array(vals), axis=0)
+        assert ry[z, y, x] == pytest.approx(mean[0], rel=1e-13, abs=1e-15)
+        assert rb[z, y, x] == pytest.approx(mean[1], rel=1e-13, abs=1e-15)
+        assert np.allclose(u[z, y, x], [v[0], v[1], 0.0], atol=1e-15)
+
+
+def test_created_density_is_the_neighbour_mean_with_ink_nearby(O):
+    """Creation next to the ink: a head moving through an ink-filled bore
+    leaves nodes whose neighbours carry different ink and air densities, so
+    a wrong neighbour set (counting the rest link, a node solid before or
+    after, or the created node itself) changes the mean."""
+    nx, ny, nz = 20, 14, 10
+    v = (0.07, 0.03)
+    cfg = W.printing((nx, ny, nz), head_x0=(6.0, 6.5), r_in=3.0, tip_z=4.0, head_v=v, u_ink=0.02, n=0.5,
+                     storage="f64")
+    ry, rb = W.nozzle_fields(cfg)
+    s = O.OracleSim(cfg, ry, rb)
+    s.step(20)
+    found = 0
+    for _ in range(60):
+        solid_before = s.solid()
+        s.step(1)
+        created = solid_before & ~s.solid()
+        if created.any():
+            _check_created_densities(s, created, solid_before, v)
+            found += int(created.sum())
+    assert found >= 10
 
 
 # ------------------------------------------------------------- Laplace

@@ -250,6 +250,51 @@ def test_recolouring_invariants(O, lat_id):
         assert (fY - fY0) @ c @ G > 0
 
 
+# Sum over the moving links of w_i c_ia c_ib / |c_i|, a multiple of delta_ab
+# on both lattices: D3Q19 has 2 axis links (w = 1/18, |c| = 1) and 8 face
+# diagonals (w = 1/36, |c| = sqrt 2) with c_a^2 = 1 per axis, i.e.
+# 2/18 + 8/(36 sqrt 2) = (1 + sqrt 2)/9; D2Q9 (in its x-z plane) 2 axis links
+# (w = 1/9) and 4 diagonals (w = 1/36), 2/9 + 4/(36 sqrt 2) = (4 + sqrt 2)/18.
+LINK_SUM = {19: (1 + np.sqrt(2)) / 9, 9: (4 + np.sqrt(2)) / 18}
+W0 = {19: 1 / 3, 9: 4 / 9}
+
+
+@pytest.mark.parametrize("lat_id", [9, 19])
+@pytest.mark.parametrize("alpha", [(None, None), (0.9, 0.5)])
+def test_recolouring_beta_term_first_moment(O, lat_id, alpha):
+    """Magnitude of the recolouring operator's beta term (Sec. II.A).  With
+    cos(phi_i) = c_i.G / (|c_i| |G|_eps) and sum_k f^{k,eq}(rho_k, 0) =
+    sum_k rho_k phi_i^k = w_i e on the moving links, e = sum_k rho_k (1 -
+    alpha_k)/(1 - w_0), its first moment is
+        sum_i (f^Y_i - (rho_Y/rho) f*_i) c_i
+            = beta (rho_Y rho_B / rho^2) (e / |G|_eps) LINK_SUM G.
+    A dropped 1/|c_i|, a wrong phi weight or a wrong density factor changes
+    the constant; checked at neutral and at unequal alpha (density ratio
+    (1 - alpha_B)/(1 - alpha_Y) = 5)."""
+    lat = O.lattice(lat_id)
+    c = lat["c"].astype(float)
+    a = (W0[lat_id], W0[lat_id]) if alpha[0] is None else alpha
+    rng = np.random.default_rng(11)
+    beta, eps = 0.7, 1e-3
+    for _ in range(6):
+        rY, rB = rng.uniform(0.05, 1.0, 2)
+        G = rng.normal(size=3) * rng.choice([1e-3, 1.0])
+        if lat["D"] == 2:
+            G[1] = 0
+        fstar = rng.uniform(0.01, 0.2, len(c))
+        fY, _ = O.recolour(lat_id, a, beta, eps, rY, rB, G, fstar)
+        fY0, _ = O.recolour(lat_id, a, 0.0, eps, rY, rB, G, fstar)
+        rho = rY + rB
+        e = (rY * (1 - a[0]) + rB * (1 - a[1])) / (1 - W0[lat_id])
+        gmag = np.sqrt(G @ G + eps * eps)
+        expect = beta * rY * rB / rho ** 2 * e / gmag * LINK_SUM[lat_id] * G
+        assert np.allclose((fY - fY0) @ c, expect, rtol=1e-13, atol=1e-17)
+        # the term is odd in c_i: no mass and no second moment
+        d = fY - fY0
+        assert abs(d.sum()) < 1e-16
+        assert np.abs(np.einsum("i,ia,ib->ab", d, c, c)).max() < 1e-16
+
+
 # -------------------------------------------------------------- rheology
 
 def _cfg(**kw):
