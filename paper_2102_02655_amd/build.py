@@ -15,7 +15,7 @@ ARCH = os.environ.get("LBPRINT_ARCH", "gfx950")
 
 
 def command(out: str = OUT) -> list:
-    return ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    return ["/opt/rocm/bin/hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"), "-o", out, SRC]
 

@@ -216,17 +216,19 @@ __device__ __forceinline__ CellState<R> cell_state(const DevParams &P, const Mom
     C.j[1] = M.m[3];
     C.j[2] = M.m[4];
     // non-equilibrium stresses: total (collision) and ink (strain rate)
-    const R iso = rY * R(P.dcs2[0]) + rB * R(P.dcs2[1]) + drho * cs2;
+    // isotropic part of the equilibrium stress, formed from the FP64 masses:
+    // at unequal alpha its terms are O(rho) and cancel to O(drho)
+    const R iso = R(M.dm[1] * P.dcs2[0] + (rho_d - M.dm[1]) * P.dcs2[1] + M.dm[0] * (1.0 / 3.0));
     C.Pi[0] = M.m[5] - iso - rho * ux * ux;
     C.Pi[1] = M.m[6] - iso - rho * uy * uy;
     C.Pi[2] = M.m[7] - iso - rho * uz * uz;
     C.Pi[3] = M.m[8] - rho * ux * uy;
     C.Pi[4] = M.m[9] - rho * ux * uz;
     C.Pi[5] = M.m[10] - rho * uy * uz;
-    const R cY2 = cs2 + R(P.dcs2[0]);
-    const R Yxx = M.m[11] - rY * (cY2 + ux * ux);
-    const R Yyy = M.m[12] - rY * (cY2 + uy * uy);
-    const R Yzz = M.m[13] - rY * (cY2 + uz * uz);
+    const R pY = R(M.dm[1] * (1.0 / 3.0 + P.dcs2[0]));  // the ink's isotropic stress, from the FP64 mass
+    const R Yxx = M.m[11] - pY - rY * ux * ux;
+    const R Yyy = M.m[12] - pY - rY * uy * uy;
+    const R Yzz = M.m[13] - pY - rY * uz * uz;
     const R Yxy = M.m[14] - rY * ux * uy;
     const R Yxz = M.m[15] - rY * ux * uz;
     const R Yyz = M.m[16] - rY * uy * uz;
@@ -304,9 +306,13 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
     K.byz = R(2) * (h * (rho * vy * vz + om * C.Pi[5]) + pn * Fcy * Fcz);
     const R a0 = R(-1.5) * (rho * (vx * vx + vy * vy + vz * vz) + om * trPi) + R(2.0 / 3.0) * pA;
     // rest-frame weights relative to w: phi_i^k - w_i = w_i kappa_k (i > 0)
-    const R kapY = R(P.phid[0][1] / lbq::w(1)), kapB = R(P.phid[1][1] / lbq::w(1));
-    K.k1 = a0 + drho + rY * kapY + rB * kapB;
-    K.t0 = R(lbq::w(0)) * (a0 + drho) + rY * R(P.phid[0][0]) + rB * R(P.phid[1][0]);
+    // (the equilibrium shifts are formed from the FP64 masses: at unequal
+    // alpha the terms are O(rho) and cancel to O(drho) on the moving links)
+    const double rB_d = rho_d - C.rY;
+    const double k1_eq = C.drho + C.rY * (P.phid[0][1] / lbq::w(1)) + rB_d * (P.phid[1][1] / lbq::w(1));
+    const double t0_eq = lbq::w(0) * C.drho + C.rY * P.phid[0][0] + rB_d * P.phid[1][0];
+    K.k1 = a0 + R(k1_eq);
+    K.t0 = R(lbq::w(0)) * a0 + R(t0_eq);
     // recolouring: beta rho_Y rho_B / rho^2 * e / |grad rho^N|_eps * grad rho^N,
     // e = sum_k rho_k (1 - alpha_k) / (1 - w_0)
     const R e = rY * R(P.phi[0][1] / lbq::w(1)) + rB * R(P.phi[1][1] / lbq::w(1));

@@ -3,8 +3,13 @@ on the same seeded inputs.
 
 Tolerances: FP64 storage, relative L2 <= 1e-10 on rho_Y, rho_B and u; FP32
 storage, relative L2 <= 1e-5 on the same fields after 1000 steps (velocity
-relative to the oracle's velocity norm over the fluid cells).
+relative to the oracle's velocity norm over the fluid cells).  The static
+droplet is the exception in FP32: its dynamics amplify rounding, so its
+FP32 bound is a fixed multiple of the oracle's own response to FP32-sized
+rounding noise (tests/golden/droplet_fp32_noise.json, see
+test_droplet_fp32).
 """
+import json
 import os
 import sys
 
@@ -73,23 +78,33 @@ def test_droplet_fp64(G, droplet_oracle):
     assert np.abs(g[3]["mom"] - f500[3]["mom"]).max() < 1e-11
 
 
+NOISE = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "droplet_fp32_noise.json")))
+# The GPU's FP32 path rounds every population after some tens of FP32
+# operations, not once: its per-step perturbation is taken as at most 32
+# times the 2^-24 storage rounding, and the droplet's response is linear in
+# the perturbation (the stored responses at 2^-24 and 2^-20 differ by 16x).
+FP32_ROUNDING_FACTOR = 32.0
+
+
 def test_droplet_fp32(G, droplet_oracle):
-    """Static droplet in FP32 storage, 1000 steps.  The droplet's spurious
-    currents amplify any rounding difference: the FP64 GPU run measures that
-    amplification (its error over the FP64 unit roundoff); the FP32 error
-    must stay within the same amplification of the FP32 unit roundoff (x4),
-    and never above 1e-3."""
+    """Static droplet in FP32 storage, 1000 steps.  Bound: FP32_ROUNDING_FACTOR
+    times the oracle's own response to FP32-sized rounding noise injected at
+    every step (measured on the oracle alone and stored); never above 1e-3.
+    FP64 storage over the same 1000 steps stays at 1e-10."""
     cfg, ry, rb, _, f1000 = droplet_oracle
     s64 = G.Sim(dict(cfg, storage="f64"), ry, rb)
     s64.step(1000)
-    e64 = compare(s64.moments(), f1000, TOL["f64"], "droplet f64 t=1000")
-    amp = [e / np.finfo(np.float64).eps for e in e64]
+    compare(s64.moments(), f1000, TOL["f64"], "droplet f64 t=1000")
+    resp = NOISE["response"]["2^-24"]["rel_l2"]
+    lin = [b / a for a, b in zip(resp, NOISE["response"]["2^-20"]["rel_l2"])]
+    assert all(8 < r < 32 for r in lin), lin  # linear response: 16x for 16x the noise
     sim = G.Sim(dict(cfg, storage="f32"), ry, rb)
     sim.step(1000)
     g = sim.moments()
     e32 = compare(g, f1000, 1e-3, "droplet f32 t=1000")
-    for a, e in zip(amp, e32):
-        assert e <= 4 * a * np.finfo(np.float32).eps, (e, a)
+    for name, r, e in zip(("rho_Y", "rho_B", "u"), resp, e32):
+        say(f"droplet f32 {name}: {e:.3e} = {e / r:.1f} x the oracle's 2^-24 noise response {r:.3e}")
+        assert e <= FP32_ROUNDING_FACTOR * r, (name, e, r)
     # FP64 conservation sums of FP32 populations
     assert np.allclose(g[3]["mass"], f1000[3]["mass"], rtol=1e-6)
 
@@ -218,7 +233,10 @@ def test_moments_do_not_disturb_the_state(G):
 @pytest.mark.timeout(900)
 def test_print_bed_full_size_first_steps(G, O):
     """The benchmark's configuration (512x256x128, FP32, moving head): three
-    steps against the oracle over the whole box, and the mass ledger."""
+    steps against the oracle over the whole box, and the FP64 mass ledger.
+    The head starts on lattice coordinates, so the cells lying exactly on its
+    inner and outer radii change class at the first step: 16 nodes are
+    created and 80 deleted, at full size as on the 128x64x32 crop."""
     cfg = W.print_bed(storage="f32")
     ry, rb = W.nozzle_fields(cfg)
     sim = G.Sim(cfg, ry, rb)
@@ -227,7 +245,10 @@ def test_print_bed_full_size_first_steps(G, O):
     s = O.OracleSim(dict(cfg, storage="f64"), ry, rb)
     s.step(3)
     o = s.moments()
-    # after three steps the velocity is small and localised: compare u in
-    # absolute terms scaled by the inlet speed as well
     compare(g, o, TOL["f32"], "print bed f32 t=3")
+    gc, oc = g[3], o[3]
+    assert oc["mass_created"].sum() > 0 and oc["mass_deleted"].sum() > 0
+    for key in ("mass", "mass_wall", "mass_open", "mass_created", "mass_deleted"):
+        for k in range(2):  # per colour: the ink's terms are 1e-3 of the air's
+            assert abs(gc[key][k] - oc[key][k]) <= 1e-5 * max(abs(oc[key][k]), 1.0), (key, k, gc[key], oc[key])
     del s
