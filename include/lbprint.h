@@ -160,6 +160,24 @@ lb_status lb_step_batch(lb_handle *const *hs, const int *nsteps, int n);
 lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype,
                      lb_conserved *cons);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): lb_moments
+ * with the same arguments, outputs and errors, whose per-call partial sums
+ * (pending boundary fluxes, deletions and creations, the fields' block sums,
+ * the final values) live in a file-scope device array of the library instead
+ * of the handle's workspace.  The array is 102.5 KB (12,816 doubles) and does
+ * not grow with the box: the read-out kernels run a fixed grid of at most
+ * 1,024 blocks, so no box is too large for it (LB_EINVAL guards the slot
+ * counts).  Each GPU holds its own copy until the process ends; its address
+ * on a device is taken once, when the first handle on that device is created
+ * (LB_EDEVICE from this call if that failed).  The call allocates and frees
+ * nothing.  Every call on one GPU shares the array: calls that overlap on one
+ * GPU (different streams or threads) race and must be serialised by the
+ * caller.  Host outputs are staged in the handle's spare population buffer,
+ * as in lb_moments. */
+lb_status lb_moments_noalloc(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype,
+                             lb_conserved *cons);
+
 /* Current step count. */
 long lb_time(const lb_handle *h);
 

@@ -187,10 +187,11 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__
                                                  double *__restrict__ slots, int first)
 {
     const HeadPos H = G->H;
-    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NSLOT] = {0, 0, 0, 0, 0, 0};
     int any = 0;
-    if (cell < P.N) {
+    // grid-stride: with one block per 256 cells each thread takes one cell
+    for (long long cell = (long long)blockIdx.x * TPB + threadIdx.x; cell < P.N;
+         cell += (long long)gridDim.x * TPB) {
         int x, y, z;
         cell_xyz(P, cell, x, y, z);
         moments_cell<R>(P, H, src, mac, momd, mom, chi, cell, x, y, z, first != 0, true, acc, any);
@@ -417,9 +418,10 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, const StepGeom *__r
                                                 double *__restrict__ part)
 {
     const HeadPos H = G->H;
-    long long cell = (long long)blockIdx.x * TPB + threadIdx.x;
     double acc[NPART] = {0, 0, 0, 0, 0, 0};
-    if (cell < P.N) {
+    // grid-stride: with one block per 256 cells each thread takes one cell
+    for (long long cell = (long long)blockIdx.x * TPB + threadIdx.x; cell < P.N;
+         cell += (long long)gridDim.x * TPB) {
         int x, y, z;
         cell_xyz(P, cell, x, y, z);
         bool solid = !far_from_head(P, H.hx_c, H.hy_c, x, y) && is_solid(P, H.hx_c, H.hy_c, x, y, z);
@@ -433,14 +435,14 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, const StepGeom *__r
             if (P.drag_gamma != 0.0 && P.face_lo == FACE_WALL && (double)z + 0.5 < P.drag_range)
                 for (int a = 0; a < 3; ++a) F[a] -= P.drag_gamma * rY * (j[a] / r - P.u_lo[a]);
             for (int a = 0; a < 3; ++a) U[a] = (j[a] + 0.5 * F[a]) / r;
-            acc[0] = rY;
-            acc[1] = rB;
-            acc[2] = j[0];
-            acc[3] = j[1];
-            acc[4] = j[2];
+            acc[0] += rY;
+            acc[1] += rB;
+            acc[2] += j[0];
+            acc[3] += j[1];
+            acc[4] += j[2];
             double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
             bool bad = !(r > 0.0) || !(uu <= 0.09) || rY != rY || rB != rB;
-            acc[5] = bad ? 1.0 : 0.0;
+            acc[5] = bad ? 1.0 : acc[5];
         }
         if (ory) ory[cell] = O(rY);
         if (orb) orb[cell] = O(rB);
@@ -471,7 +473,7 @@ __global__ void k_clock(DevParams P, StepGeom *__restrict__ G)
 __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part, const double *__restrict__ pend,
                                                 long long nbm, const double *__restrict__ cumpre, int nbp,
                                                 const double *__restrict__ cumc, const double *__restrict__ pendc,
-                                                int nbs, double *__restrict__ out)
+                                                int nbs, int nbsp, double *__restrict__ out)
 {
     double v[14] = {0};
     for (long long b = threadIdx.x; b < nbm; b += TPB) {
@@ -496,8 +498,8 @@ __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part,
         v[12] += c[5];
     }
     for (int b = threadIdx.x; b < nbs; b += TPB) {
-        v[9] += cumc[2 * b] + pendc[2 * b];
-        v[10] += cumc[2 * b + 1] + pendc[2 * b + 1];
+        v[9] += cumc[2 * b] + (b < nbsp ? pendc[2 * b] : 0.0);
+        v[10] += cumc[2 * b + 1] + (b < nbsp ? pendc[2 * b + 1] : 0.0);
     }
     __shared__ double red[14][TPB];
     for (int q = 0; q < 14; ++q) red[q][threadIdx.x] = v[q];
@@ -773,6 +775,10 @@ struct lb_handle {
     int first;
     int unstable;
     std::string err;
+    // lb_moments_noalloc: this device's copy of the static scratch array
+    // (null with scratch_err set if its address could not be taken)
+    double *scratch = nullptr;
+    std::string scratch_err;
     // kernel timing (lb_timing): three events per timed step
     int timing = 0;
     std::vector<hipEvent_t> ev;
@@ -863,24 +869,41 @@ R *mac_at(lb_handle *h, long t)
     return as<R>(h, h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.N * sizeof(R)));
 }
 
+// Where one read-out keeps its per-call partial sums: the pending boundary
+// fluxes and deletions of the pull (nb blocks x NSLOT), the fields' sums
+// (nb blocks x NPART), the pending created mass (NB_SPARSE x 2) and the 14
+// final values.  lb_moments uses slots in the handle's workspace and one
+// block per 256 cells; lb_moments_noalloc the library's static device array
+// and a fixed grid.
+struct ReadSlots {
+    double *pend, *part, *pendc, *red;
+    unsigned nb;          // blocks of the whole-box read-out kernels
+    bool zero_pendc;      // clear pendc when no creation is pending (else count no slot)
+};
+
 // Read-out pull: moments of the whole box at the current step, pending
-// fluxes / deletions / creations (nothing committed).
+// fluxes / deletions / creations (nothing committed).  Returns the number of
+// pending-creation slots written (k_reduce reads that many).
 template <typename R, int ST>
-lb_status run_readout(lb_handle *h)
+lb_status run_readout(lb_handle *h, const ReadSlots &S, int &nbsp)
 {
     const Layout &L = h->L;
     if (lb_status s = launch_clock(h)) return s;
-    hipLaunchKernelGGL((k_moments<R, ST>), dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
+    hipLaunchKernelGGL((k_moments<R, ST>), dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
                        pop_src<R, ST>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
-                       as<R>(h, L.chi), as<double>(h, L.pend), h->first);
+                       as<R>(h, L.chi), S.pend, h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
         hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
-                           as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.pendc), 0);
+                           as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pendc, 0);
         if (lb_status s = check_launch(h, "k_create")) return s;
-    } else {
-        if (hipMemsetAsync(as<double>(h, L.pendc), 0, NB_SPARSE * 2 * 8, h->stream) != hipSuccess)
+        nbsp = S.zero_pendc ? NB_SPARSE : (int)L.nb_create;
+    } else if (S.zero_pendc) {
+        if (hipMemsetAsync(S.pendc, 0, NB_SPARSE * 2 * 8, h->stream) != hipSuccess)
             return fail(h, LB_EDEVICE, "hipMemsetAsync");
+        nbsp = NB_SPARSE;
+    } else {
+        nbsp = 0;
     }
     return LB_OK;
 }
@@ -1002,19 +1025,28 @@ lb_status run_step(lb_handle *h)
 }
 
 template <typename R, typename O>
-lb_status run_output(lb_handle *h, O *ry, O *rb, O *u)
+lb_status run_output(lb_handle *h, const ReadSlots &S, O *ry, O *rb, O *u)
 {
-    hipLaunchKernelGGL((k_output<R, O>), dim3((unsigned)h->L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
-                       as<double>(h, h->L.momd), as<R>(h, h->L.mom), ry, rb, u, as<double>(h, h->L.part));
+    hipLaunchKernelGGL((k_output<R, O>), dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
+                       as<double>(h, h->L.momd), as<R>(h, h->L.mom), ry, rb, u, S.part);
     return check_launch(h, "k_output");
 }
 
+ReadSlots workspace_slots(lb_handle *h)
+{
+    const Layout &L = h->L;
+    return ReadSlots{as<double>(h, L.pend), as<double>(h, L.part), as<double>(h, L.pendc), as<double>(h, L.red),
+                     (unsigned)L.nbm, true};
+}
+
 template <typename R, int ST>
-lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype, lb_conserved *cons)
+lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype, lb_conserved *cons,
+                       const ReadSlots &S)
 {
     const Layout &L = h->L;
     const long long N = h->P.N;
-    if (lb_status s = run_readout<R, ST>(h)) return s;
+    int nbsp = 0;
+    if (lb_status s = run_readout<R, ST>(h, S, nbsp)) return s;
     // outputs: direct to device pointers, or staged in the spare population buffer
     char *stage = pops_at(h, 1 - h->cur);
     size_t osz = dtype == 0 ? 8 : 4;
@@ -1024,15 +1056,14 @@ lb_status moments_impl(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, i
         drb = rb ? stage + N * osz : nullptr;
         du = u ? stage + 2 * N * osz : nullptr;
     }
-    lb_status s = dtype == 0 ? run_output<R, double>(h, (double *)dry, (double *)drb, (double *)du)
-                             : run_output<R, float>(h, (float *)dry, (float *)drb, (float *)du);
+    lb_status s = dtype == 0 ? run_output<R, double>(h, S, (double *)dry, (double *)drb, (double *)du)
+                             : run_output<R, float>(h, S, (float *)dry, (float *)drb, (float *)du);
     if (s) return s;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, h->stream, as<double>(h, L.part), as<double>(h, L.pend),
-                       L.nbm, as<double>(h, L.cumpre), NB_PRE, as<double>(h, L.cumc), as<double>(h, L.pendc),
-                       NB_SPARSE, as<double>(h, L.red));
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(TPB), 0, h->stream, S.part, S.pend, (long long)S.nb,
+                       as<double>(h, L.cumpre), NB_PRE, as<double>(h, L.cumc), S.pendc, NB_SPARSE, nbsp, S.red);
     if ((s = check_launch(h, "k_reduce"))) return s;
     double red[16];
-    hipError_t e = hipMemcpyAsync(red, as<double>(h, L.red), 14 * 8, hipMemcpyDeviceToHost, h->stream);
+    hipError_t e = hipMemcpyAsync(red, S.red, 14 * 8, hipMemcpyDeviceToHost, h->stream);
     if (!dst_dev && e == hipSuccess) {
         if (ry) e = hipMemcpyAsync(ry, dry, N * osz, hipMemcpyDeviceToHost, h->stream);
         if (rb && e == hipSuccess) e = hipMemcpyAsync(rb, drb, N * osz, hipMemcpyDeviceToHost, h->stream);
@@ -1080,7 +1111,85 @@ lb_status step_one(lb_handle *h)
 
 lb_status moments_any(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype, lb_conserved *cons)
 {
-    return with_storage(h, [&]<typename R, int ST>() { return moments_impl<R, ST>(h, ry, rb, u, dst_dev, dtype, cons); });
+    const ReadSlots S = workspace_slots(h);
+    return with_storage(h, [&]<typename R, int ST>() {
+        return moments_impl<R, ST>(h, ry, rb, u, dst_dev, dtype, cons, S);
+    });
+}
+
+// ------------------------------------------------ read-out without scratch
+//
+// lb_moments_noalloc keeps the read-out's per-call partial sums in `scratch`,
+// a file-scope device array of NA_TOTAL doubles (102.5 KB), instead of the
+// handle's workspace, with a fixed grid of at most NB_NA blocks (grid-stride
+// kernels), so its size does not depend on the box.  Each GPU the library
+// runs on holds its own copy until the process ends.  In host code the
+// array's name is not a device address: the kernels get each device's copy
+// through the pointer hipGetSymbolAddress returned for that device
+// (scratch_dev), taken once per device at lb_create.  Every call on one GPU
+// shares the array; the kernels write every slot they read, so nothing has
+// to be cleared, and calls that overlap on one GPU race.
+constexpr int NB_NA = 1024;
+constexpr size_t NA_PEND = 0;
+constexpr size_t NA_PART = NA_PEND + (size_t)NB_NA * NSLOT;
+constexpr size_t NA_PENDC = NA_PART + (size_t)NB_NA * NPART;
+constexpr size_t NA_RED = NA_PENDC + (size_t)NB_SPARSE * 2;
+constexpr size_t NA_TOTAL = NA_RED + 16;
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[NA_TOTAL];
+
+namespace {
+
+// The device address of `scratch` on device `dev` (looked up once per
+// device, with that device current).
+lb_status scratch_dev(int dev, double **out, std::string &err)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        err = "device index out of range";
+        return LB_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) {
+            err = "hipGetDevice failed";
+            return LB_EDEVICE;
+        }
+        if (cur != dev && hipSetDevice(dev) != hipSuccess) {
+            err = "hipSetDevice failed";
+            return LB_EDEVICE;
+        }
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return LB_EDEVICE;
+        }
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return LB_OK;
+}
+
+lb_status moments_noalloc_any(lb_handle *h, void *ry, void *rb, void *u, int dst_dev, int dtype,
+                              lb_conserved *cons)
+{
+    if (!h->scratch) return fail(h, LB_EDEVICE, "lb_moments_noalloc: no device scratch: " + h->scratch_err);
+    const long long nb = std::min<long long>(h->L.nbm, NB_NA);
+    if (nb > NB_NA || (long long)h->L.nb_create > NB_SPARSE)
+        return fail(h, LB_EINVAL, "lb_moments_noalloc: the read-out needs more slots than the device scratch holds");
+    double *sc = h->scratch;
+    const ReadSlots S{sc + NA_PEND, sc + NA_PART, sc + NA_PENDC, sc + NA_RED, (unsigned)nb, false};
+    return with_storage(h, [&]<typename R, int ST>() {
+        return moments_impl<R, ST>(h, ry, rb, u, dst_dev, dtype, cons, S);
+    });
 }
 
 // ---------------------------------------------------------------- batching
@@ -1179,6 +1288,15 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     h->t = 0;
     h->first = 1;
     h->unstable = 0;
+    {
+        // the device of the workspace: where lb_moments_noalloc's scratch lives
+        hipPointerAttribute_t attr;
+        int dev = -1;
+        if (hipPointerGetAttributes(&attr, dev_workspace) == hipSuccess) dev = attr.device;
+        else (void)hipGetLastError();
+        if (dev < 0) (void)hipGetDevice(&dev);
+        if (scratch_dev(dev, &h->scratch, h->scratch_err) != LB_OK) h->scratch = nullptr;
+    }
     const long long N = h->P.N;
     // stage the initial fields in the second population buffer (at least
     // 76 B per cell, the fields need 40)
@@ -1241,6 +1359,13 @@ lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is
 {
     if (!h || (dtype != 0 && dtype != 1)) return fail(h, LB_EINVAL, "bad handle or dtype");
     return moments_any(h, rho_y, rho_b, u, dst_is_device, dtype, cons);
+}
+
+lb_status lb_moments_noalloc(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype,
+                             lb_conserved *cons)
+{
+    if (!h || (dtype != 0 && dtype != 1)) return fail(h, LB_EINVAL, "bad handle or dtype");
+    return moments_noalloc_any(h, rho_y, rho_b, u, dst_is_device, dtype, cons);
 }
 
 long lb_time(const lb_handle *h) { return h ? h->t : -1; }

@@ -19,8 +19,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16dev": 2, "f16dev": 3}
 RHEOLOGY = {"newtonian": 0, "power_law": 1, "cross": 2}
 FACE = {"periodic": 0, "wall": 1, "pressure": 2}
 
-EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_time", "lb_timing",
-           "lb_timing_read", "lb_destroy", "lb_strerror", "lb_last_error")
+EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc", "lb_time",
+           "lb_timing", "lb_timing_read", "lb_destroy", "lb_strerror", "lb_last_error")
 
 _d2 = C.c_double * 2
 _d3 = C.c_double * 3
@@ -95,6 +95,7 @@ def lib():
         L.lb_step.argtypes = [vp, C.c_int]
         L.lb_step_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), C.c_int]
         L.lb_moments.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Conserved)]
+        L.lb_moments_noalloc.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Conserved)]
         L.lb_time.argtypes = [vp]
         L.lb_time.restype = C.c_long
         L.lb_timing.argtypes = [vp, C.c_int]
@@ -104,8 +105,8 @@ def lib():
         L.lb_strerror.restype = C.c_char_p
         L.lb_last_error.argtypes = [vp]
         L.lb_last_error.restype = C.c_char_p
-        for f in ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_timing", "lb_timing_read",
-                  "lb_destroy"):
+        for f in ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc",
+                  "lb_timing", "lb_timing_read", "lb_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -280,3 +281,4 @@ class Sim:
             self.close()
         except Exception:
             pass
+
