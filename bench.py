@@ -61,9 +61,39 @@ def measured_traffic(storage: str):
     return float(m_b.group(1))
 
 
-def cpu_baseline(seconds: float = 15.0):
-    """The FP64 oracle on the 128x64x32 crop of the same set-up, as many steps
-    as fit in about `seconds`, on all host threads."""
+def host_cpu():
+    """CPU model, logical CPUs and physical cores of this host (from
+    /proc/cpuinfo: distinct (physical id, core id) pairs)."""
+    model, cores, logical = None, set(), 0
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                elif not k and phys is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": logical or os.cpu_count(), "physical_cores": len(cores) or None}
+
+
+def cpu_baseline(seconds: float = 15.0, full_box: bool = False):
+    """The FP64 oracle on the 128x64x32 crop of the same set-up: three timed
+    runs of about seconds/4 each on all the oracle's threads (median
+    reported), then a single-thread run; with full_box, also 20 steps of the
+    whole 512x256x128 box (about 15 GB of host memory, a minute of CPU)."""
     from oracle import oracle as O
     from paper_2102_02655_amd import workloads as W
 
@@ -72,15 +102,38 @@ def cpu_baseline(seconds: float = 15.0):
     s = O.OracleSim(cfg, ry, rb)
     s.step(1)
     cells = cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2]
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < seconds:
-        s.step(2)
-        steps += 2
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"128x64x32 crop of the print-bed set-up, {steps} steps after 1 warm-up, FP64"}
+    threads = O.threads()
+
+    def timed(budget):
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < budget:
+            s.step(2)
+            steps += 2
+        return cells * steps / (time.perf_counter() - t0) / 1e6, steps
+
+    runs = [timed(seconds / 4) for _ in range(3)]
+    rates = sorted(r for r, _ in runs)
+    O.set_threads(1)
+    one, one_steps = timed(seconds / 4)
+    O.set_threads(threads)
+    out = {"value": rates[1], "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"128x64x32 crop of the print-bed set-up, FP64, median of 3 runs of "
+                     f"{'/'.join(str(n) for _, n in runs)} steps on {threads} threads after 1 warm-up step",
+           "runs_MLUPS": [r for r, _ in runs], "one_thread_MLUPS": one, "one_thread_steps": one_steps}
+    out.update(host_cpu())
+    del s
+    if full_box:
+        cfg = W.print_bed(storage="f64")
+        ry, rb = W.nozzle_fields(cfg)
+        s = O.OracleSim(cfg, ry, rb)
+        s.step(1)
+        t0 = time.perf_counter()
+        s.step(20)
+        dt = time.perf_counter() - t0
+        out["full_box_MLUPS"] = 512 * 256 * 128 * 20 / dt / 1e6
+        out["full_box_sample"] = "20 steps of the 512x256x128 print bed after 1 warm-up step"
+    return out
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 3):
@@ -242,6 +295,8 @@ def main():
     ap.add_argument("--workload", default="print_bed", choices=["print_bed", "largest"],
                     help="print_bed: the 512x256x128 benchmark; largest: the 1024x512x384 domain")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on 20 steps of the whole 512x256x128 box (about 15 GB of host memory)")
     ap.add_argument("--copy-probe", action="store_true", help="first run a plain copy of known size (PMC scaling)")
     ap.add_argument("--serve", action="store_true", help="run the serving sweep instead of the step benchmark")
     ap.add_argument("--serve-count", type=int, default=256)
@@ -319,7 +374,7 @@ def main():
         "mass": list(map(float, cons["mass"])),
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(full_box=args.cpu_full)
     print(json.dumps(out), flush=True)
 
 

@@ -1067,6 +1067,26 @@ int lbo_velocity_index(lbo_sim *s, int *c)
 
 long lbo_time(lbo_sim *s) { return s ? s->t : -1; }
 
+/* Threads the OpenMP loops use (1 without OpenMP), and a way to change it
+ * (the CPU baseline's single-thread leg). */
+int lbo_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void lbo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void lbo_destroy(lbo_sim *s)
 {
     if (!s) return;

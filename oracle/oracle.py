@@ -104,6 +104,10 @@ def lib():
         L.lbo_time.restype = C.c_long
         L.lbo_destroy.argtypes = [C.c_void_p]
         L.lbo_destroy.restype = None
+        L.lbo_threads.argtypes = []
+        L.lbo_threads.restype = C.c_int
+        L.lbo_set_threads.argtypes = [C.c_int]
+        L.lbo_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -242,6 +246,15 @@ def gradient(lat: int, chi: np.ndarray) -> np.ndarray:
     out = np.zeros(chi.shape + (3,))
     assert lib().lbo_gradient(lat, nx, ny, nz, _dp(chi), _dp(out)) == 0
     return out
+
+
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().lbo_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().lbo_set_threads(int(n))
 
 
 # ------------------------------------------------------------------ simulation

@@ -2,7 +2,8 @@
 lattice Boltzmann theory fix: conservation laws, exact streaming, closed-form
 channel flows, the inlet's mass flux, the pressure boundary's fixed point,
 the moving template's node creation, Laplace's law with sigma = 2 tau A / 9,
-and the neutral (90 degree) contact angle of zeta = 1 walls.
+the substrate drag (Brinkman's profile), the neutral (90 degree) contact
+angle of zeta = 1 walls and the contact angle of Eq. (wet2) for zeta != 1.
 """
 import numpy as np
 import pytest
@@ -428,6 +429,63 @@ def test_laplace_law_cylinders(O, lat):
 
 
 # --------------------------------------------------------------- wetting
+
+def _sessile_drop(O, zeta, nx=96, nz=40, R=18.0, zc0=-0.5):
+    cfg = W.base_params((nx, 1, nz), lattice=9, alpha=(4 / 9, 4 / 9), tau_b=1.0, tau_y=1.0, face_zlo="wall",
+                        face_zhi="wall", zeta_wall=zeta)
+    z, x = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    ins = np.hypot(x - (nx - 1) / 2, z - zc0) <= R
+    return O.OracleSim(cfg, np.where(ins, 1.0, 0.0)[:, None, :], np.where(ins, 0.0, 1.0)[:, None, :])
+
+
+def _drop_angle_and_wall_densities(s, zeta):
+    """The ink drop's contact angle from its shape (a circular cap through
+    the apex height h and the contact half-width a on the first fluid layer,
+    both from the rho^N = 0 crossings, the wall at z = -1/2), and the wall's
+    fictitious densities at the contact point, Eq. (wet): zeta^k times the
+    w-weighted mean of rho^k over the wall node's fluid neighbours (D2Q9:
+    the three nodes above it), interpolated between the two wall nodes that
+    bracket the contact point."""
+    ry, rb, _, _ = s.moments()
+    ry, rb = ry[:, 0, :], rb[:, 0, :]
+    nz, nx = ry.shape
+    xc = (nx - 1) / 2
+    N = (ry - rb) / (ry + rb)
+    col = 0.5 * (N[:, nx // 2 - 1] + N[:, nx // 2])
+    iz = np.where(col < 0)[0][0]
+    h = iz - 1 + col[iz - 1] / (col[iz - 1] - col[iz]) + 0.5
+    row = N[0, :]
+    ix = np.where(row[nx // 2:] < 0)[0][0] + nx // 2
+    a = ix - 1 + row[ix - 1] / (row[ix - 1] - row[ix]) - xc
+    theta = np.degrees(2 * np.arctan(h / a))
+    xcp = xc + a
+    w = {-1: 1 / 36, 0: 1 / 9, 1: 1 / 36}
+    rs = []
+    for xw in (int(np.floor(xcp)), int(np.floor(xcp)) + 1):
+        den = sum(w.values())
+        rs.append([zeta[k] * sum(w[d] * f[0, (xw + d) % nx] for d in w) / den for k, f in enumerate((ry, rb))])
+    fr = xcp - np.floor(xcp)
+    sY = (1 - fr) * rs[0][0] + fr * rs[1][0]
+    sB = (1 - fr) * rs[0][1] + fr * rs[1][1]
+    return theta, sY, sB
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("zeta", [(1.2, 1.0), (0.85, 1.0)])
+def test_wetting_contact_angle_follows_eq_wet2(O, zeta):
+    """Non-neutral walls (zeta != 1 in Eq. (wet)): an ink drop started as a
+    half disc relaxes to the angle Eq. (wet2) gives for the wall densities
+    at its contact point, theta_B = arccos((rho_sB - rho_sY) / rho_B^0), read
+    as the angle inside the air, i.e. an ink angle of 180 - theta_B (within
+    4 degrees; measured 2-3).  zeta_Y > 1 makes the wall hydrophilic for the
+    ink (angle below 90), zeta_Y < 1 hydrophobic."""
+    s = _sessile_drop(O, zeta)
+    s.step(8000)
+    theta, sY, sB = _drop_angle_and_wall_densities(s, zeta)
+    pred = 180.0 - np.degrees(np.arccos(np.clip((sB - sY) / 1.0, -1.0, 1.0)))
+    assert abs(theta - pred) < 4.0, (theta, pred, sY, sB)
+    assert (theta - 90.0) * (1.0 - zeta[0]) > 0 and abs(theta - 90.0) > 3.0
+
 
 @pytest.mark.slow
 def test_neutral_wetting_contact_angle(O):
