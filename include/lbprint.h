@@ -151,6 +151,43 @@ lb_status lb_step(lb_handle *h, int nsteps);
  * a graph call fails.  The cached graphs are released by lb_destroy. */
 lb_status lb_step_batch(lb_handle *const *hs, const int *nsteps, int n);
 
+/* Batches (serving, a parameter sweep of many simulations): one launch of
+ * each step kernel advances every member of a batch.  A batch holds a slot
+ * table in device memory -- per member its parameters, its buffers for both
+ * step parities and the range of blocks it owns in each kernel's grid -- and
+ * one HIP graph of k steps of the five batched kernels (boundary preparation,
+ * node creation, wall densities, ghost layers, the fused step), captured once
+ * and replayed; it is captured again only when the step count or a kernel's
+ * block count outgrows it.  Every block runs its member's kernel body with
+ * its block index within the member's share, which is the grid the member
+ * uses alone, so every member's fields and FP64 sums are bit-identical to
+ * stepping it alone with lb_step.
+ *
+ * lb_batch_footprint: bytes of device workspace a batch needs (the slot table
+ * of at most 64 members; pure host computation).
+ * lb_batch_create: storage is the lb_storage form every member must have;
+ * dev_workspace (>= lb_batch_footprint bytes, 256-byte aligned) is lent to the
+ * batch until lb_batch_destroy; hip_stream is the batch's stream.  The batch
+ * also keeps two pinned host buffers for staging the table (hipHostMalloc).
+ * lb_batch_step: advance hs[i] by nsteps[i] steps (n <= 64 distinct handles of
+ * the batch's storage form, any sizes and parameters, check_interval 0).  A
+ * member's first step (it reads its initial state) runs as an ordinary launch;
+ * the rest run in the graph, where a member with fewer steps than the graph
+ * sits out the later ones.  The batch stream waits for each member's stream
+ * first, and each member's stream waits for the batch afterwards, so calls
+ * on the handles keep their order.  Asynchronous; LB_EINVAL on bad arguments,
+ * LB_ESTATE for an unstable member, LB_EDEVICE if a HIP call fails (message in
+ * lb_batch_last_error).  The table is rebuilt at every call, so members may
+ * join, leave or be destroyed between calls.
+ * lb_batch_destroy: waits for the batch stream, releases the graph, events and
+ * staging buffers (not the workspace or the members). */
+typedef struct lb_batch lb_batch;
+lb_status lb_batch_footprint(size_t *bytes);
+lb_status lb_batch_create(int storage, void *dev_workspace, size_t ws_bytes, void *hip_stream, lb_batch **out);
+lb_status lb_batch_step(lb_batch *b, lb_handle *const *hs, const int *nsteps, int n);
+lb_status lb_batch_destroy(lb_batch *b);
+const char *lb_batch_last_error(const lb_batch *b);
+
 /* Fields and conserved sums at the current step.  rho_y, rho_b (N values) and
  * u (3N values, the physical velocity (sum f c + F/2) / rho) are written as
  * FP64 (dtype 0) or FP32 (dtype 1) into host (dst_is_device = 0) or device

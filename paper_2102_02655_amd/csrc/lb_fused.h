@@ -155,20 +155,22 @@ __device__ __forceinline__ bool macro_needed(const DevParams &P, const HeadPos &
     return dx <= lim && dy <= lim;
 }
 
+// Body of the single-role step kernel for block `bid` of `nblk` (the
+// standalone kernel passes its own block index; the batched kernel the
+// block's index within its simulation's share of the grid).
 template <typename R, int TY, bool FIRST>
-__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeom *__restrict__ G,
-                                                            FusedGrid FG, const R *__restrict__ src,
-                                                            R *__restrict__ dst,
-                                                            const double *__restrict__ momd,
-                                                            const R *__restrict__ mom, const R *__restrict__ chi,
-                                                            const R *__restrict__ ghost, R *__restrict__ mac_next)
+__device__ __forceinline__ void fused_body(const DevParams &P, StepGeom *__restrict__ G, const FusedGrid &FG,
+                                           const R *__restrict__ src, R *__restrict__ dst,
+                                           const double *__restrict__ momd, const R *__restrict__ mom,
+                                           const R *__restrict__ chi, const R *__restrict__ ghost,
+                                           R *__restrict__ mac_next, int bid, int nblk)
 {
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     const HeadPos H = G->H;
     const Box3 head = G->bx[0];
     // the last kernel of the step advances the device step counter (the
     // fields read above are not written by it)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         G->t += 1;
         G->first = 0;
     }
@@ -179,8 +181,8 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeo
     // XCD-aware order: consecutive blocks go round-robin over the 8 XCDs, so
     // block b handles tile (b % 8) * (nb / 8) + b / 8 and each XCD works on a
     // contiguous band of tiles.
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
+    const int nb = nblk;
+    const int b = bid;
     const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
     const int tx = t % FG.ntx, ty = (t / FG.ntx) % FG.nty, tz = t / (FG.ntx * FG.nty);
     const int x0 = tx * 64, y0 = ty * TY, z0 = tz * FG.zlen;
@@ -364,6 +366,17 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeo
     }
 }
 
+template <typename R, int TY, bool FIRST>
+__global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeom *__restrict__ G,
+                                                            FusedGrid FG, const R *__restrict__ src,
+                                                            R *__restrict__ dst,
+                                                            const double *__restrict__ momd,
+                                                            const R *__restrict__ mom, const R *__restrict__ chi,
+                                                            const R *__restrict__ ghost, R *__restrict__ mac_next)
+{
+    fused_body<R, TY, FIRST>(P, G, FG, src, dst, momd, mom, chi, ghost, mac_next, blockIdx.x, gridDim.x);
+}
+
 // Producer/consumer form of the march.  Waves 0 .. TY + 2 are loaders (the
 // tile rows, the two ring rows, the two ring columns as above): they pull and
 // reduce plane p, keeping the loads of plane p + 1 in flight meanwhile (FP32),
@@ -375,16 +388,12 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeo
 // plane.  Loads and stores are issued by different waves, so neither waits
 // behind the other in a wave's queue of outstanding memory operations.
 template <typename R, int TY, bool FIRST, int ST = ST_PLAIN, int CR = 1>
-__global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevParams P, StepGeom *__restrict__ G,
-                                                                  FusedGrid FG, const void *__restrict__ src,
-                                                                  void *__restrict__ dst,
-                                                                  const double *__restrict__ momd,
-                                                                  const R *__restrict__ mom,
-                                                                  const R *__restrict__ chi,
-                                                                  const R *__restrict__ ghost,
-                                                                  R *__restrict__ mac_next,
-                                                                  const float *__restrict__ mo_src,
-                                                                  float *__restrict__ mo_dst)
+__device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__restrict__ G, const FusedGrid &FG,
+                                              const void *__restrict__ src, void *__restrict__ dst,
+                                              const double *__restrict__ momd, const R *__restrict__ mom,
+                                              const R *__restrict__ chi, const R *__restrict__ ghost,
+                                              R *__restrict__ mac_next, const float *__restrict__ mo_src,
+                                              float *__restrict__ mo_dst, int bid, int nblk)
 {
     // E: stored element type; reduced storage keeps 16-bit deviations and
     // decodes them with the source cells' moments (an LDS ring of planes, the
@@ -398,7 +407,7 @@ __global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevPara
     const Box3 head = G->bx[0];
     // the last kernel of the step advances the device step counter (the
     // fields read above are not written by it)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         G->t += 1;
         G->first = 0;
     }
@@ -407,8 +416,8 @@ __global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevPara
     __shared__ R mo_r[4][NMOMR][NI];       // the other raw moments m[2..16]
     __shared__ unsigned char st_ok[4][NI];
 
-    const int nb = gridDim.x;
-    const int b = blockIdx.x;
+    const int nb = nblk;
+    const int b = bid;
     const int t = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
     const int tx = t % FG.ntx, ty = (t / FG.ntx) % FG.nty, tz = t / (FG.ntx * FG.nty);
     const int x0 = tx * 64, y0 = ty * TY, z0 = tz * FG.zlen;
@@ -725,6 +734,22 @@ __global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevPara
         reduce(p + 1, bT, bY);
         __syncthreads();
     }
+}
+
+template <typename R, int TY, bool FIRST, int ST = ST_PLAIN, int CR = 1>
+__global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void k_fused_pc(DevParams P, StepGeom *__restrict__ G,
+                                                                  FusedGrid FG, const void *__restrict__ src,
+                                                                  void *__restrict__ dst,
+                                                                  const double *__restrict__ momd,
+                                                                  const R *__restrict__ mom,
+                                                                  const R *__restrict__ chi,
+                                                                  const R *__restrict__ ghost,
+                                                                  R *__restrict__ mac_next,
+                                                                  const float *__restrict__ mo_src,
+                                                                  float *__restrict__ mo_dst)
+{
+    fused_pc_body<R, TY, FIRST, ST, CR>(P, G, FG, src, dst, momd, mom, chi, ghost, mac_next, mo_src, mo_dst,
+                                        blockIdx.x, gridDim.x);
 }
 
 }  // namespace lbk

@@ -1,15 +1,22 @@
 // lbprint.hip -- gfx950 kernels and the C ABI (include/lbprint.h) of the
 // colour-gradient lattice Boltzmann printing step (arXiv:2102.02655).
 //
-// One time step t-1 -> t is four kernels on the caller's stream:
-//   k_moments  pull f(t) from the post-collision state of t-1 (Eq. (lbm),
-//              boundary rules of Sec. II.B), reduce it to the moment set,
-//              colour fields; deleted nodes' mass and boundary fluxes (FP64)
+// One time step t-1 -> t on the caller's stream:
+//   k_pre      the step's geometry (head position, boundary boxes) from the
+//              device step counter; pulls the cells whose links touch a
+//              boundary with the rules of Sec. II.B (z faces, the head's
+//              box), their moments and colour fields; deleted nodes' mass
+//              and boundary fluxes into FP64 per-block sums
 //   k_create   nodes released by the moving head: f^eq(rho_bar, v_nozzle)
-//   k_wall     fictitious wall densities, Eq. (wet), in-box and ghost layers
-//   k_collide  colour gradient (Eq. (lattgrad)), rheology, regularised
-//              collision, perturbation, recolouring; store at the cell
+//   k_wall     the head's fictitious wall densities, Eq. (wet)
+//   k_ghost    colour fields of the ghost layers beyond the z faces
+//   k_fused_pc every other cell (lb_fused.h): pull, moments, colour stencil
+//              (Eq. (lattgrad)), rheology, regularised collision,
+//              perturbation, recolouring, store; advances the step counter
 // The stored state between steps is the post-collision population pair.
+// Read-out (k_moments, k_create, k_output, k_reduce) pulls the whole box
+// without committing anything.  Batched stepping runs the same kernel bodies
+// for many simulations per launch (kb_*, over a device slot table).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -21,6 +28,9 @@
 #include <vector>
 #include <mutex>
 #include <algorithm>
+#include <cstddef>
+#include <limits>
+#include <memory>
 
 #include "../../include/lbprint.h"
 #include "lb_collide.h"
@@ -206,18 +216,19 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__
 // boundary rule adds and the mass of nodes the head covers are added to the
 // block's cumulative slot.  Boxes 1 and 2 skip cells of box 0 (the head box)
 // so that no cell is counted twice.
+// (body for block bid of nblk; the standalone kernel below and the batched
+// kernel call it)
 template <typename R, int ST>
-__global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__ G, PopSrc<R, ST> src,
-                                             const R *__restrict__ mac, double *__restrict__ momd,
-                                             R *__restrict__ mom, R *__restrict__ chi, double *__restrict__ slots,
-                                             int first)
+__device__ __forceinline__ void pre_body(const DevParams &P, StepGeom *__restrict__ G, const PopSrc<R, ST> &src,
+                                         const R *__restrict__ mac, double *__restrict__ momd, R *__restrict__ mom,
+                                         R *__restrict__ chi, double *__restrict__ slots, int first, int bid, int nblk)
 {
     // the step's geometry from the device step counter (every block), kept
     // in memory by block 0 for the step's later kernels
     __shared__ StepGeom sg;
     if (threadIdx.x == 0) make_geom(P, G->t, G->first, sg);
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x == 0) *G = sg;
+    if (bid == 0 && threadIdx.x == 0) *G = sg;
     const HeadPos H = sg.H;
     const Box3 b0 = sg.bx[0], b1 = sg.bx[1], b2 = sg.bx[2];
     const int nbox = sg.nbox;
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__
     for (int bi = 0; bi < nbox; ++bi) {
         const Box3 B = bi == 0 ? b0 : (bi == 1 ? b1 : b2);
         const long long total = (long long)B.w * B.h * B.d;
-        for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+        for (long long k = (long long)bid * TPB + threadIdx.x; k < total; k += (long long)nblk * TPB) {
             int ix = (int)(k % B.w), iy = (int)((k / B.w) % B.h), iz = (int)(k / ((long long)B.w * B.h));
             int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
             if (z < 0 || z >= P.nz) continue;
@@ -235,7 +246,16 @@ __global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__
         }
     }
     if (!__syncthreads_or(any)) return;
-    block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, true);
+    block_sum<NSLOT>(acc, slots + (long long)bid * NSLOT, true);
+}
+
+template <typename R, int ST>
+__global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__ G, PopSrc<R, ST> src,
+                                             const R *__restrict__ mac, double *__restrict__ momd,
+                                             R *__restrict__ mom, R *__restrict__ chi, double *__restrict__ slots,
+                                             int first)
+{
+    pre_body<R, ST>(P, G, src, mac, momd, mom, chi, slots, first, blockIdx.x, gridDim.x);
 }
 
 // Sec. II.B: nodes released by the head (solid at t-1, fluid at t) start at
@@ -243,15 +263,15 @@ __global__ __launch_bounds__(TPB) void k_pre(DevParams P, StepGeom *__restrict__
 // neighbours fluid at both steps (pure air rho_B^0 if there is none).  Only
 // the moment set and the colour fields are needed downstream.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_create(DevParams P, const StepGeom *__restrict__ G,
-                                                double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
-                                                double *__restrict__ slots, int commit)
+__device__ __forceinline__ void create_body(const DevParams &P, const StepGeom *__restrict__ G,
+                                            double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
+                                            double *__restrict__ slots, int commit, int bid, int nblk)
 {
     const HeadPos H = G->H;
     const int bx0 = G->hb.x0, by0 = G->hb.y0, bz0 = G->hb.z0, bw = G->hb.w, bh = G->hb.h, bd = G->hb.d;
     double acc[2] = {0.0, 0.0};
     const long long total = (long long)bw * bh * bd;
-    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+    for (long long k = (long long)bid * TPB + threadIdx.x; k < total; k += (long long)nblk * TPB) {
         int ix = (int)(k % bw), iy = (int)((k / bw) % bh), iz = (int)(k / ((long long)bw * bh));
         int x = ((bx0 + ix) % P.nx + P.nx) % P.nx, y = ((by0 + iy) % P.ny + P.ny) % P.ny, z = bz0 + iz;
         if (z < 0 || z >= P.nz) continue;
@@ -298,19 +318,27 @@ __global__ __launch_bounds__(TPB) void k_create(DevParams P, const StepGeom *__r
         acc[0] += rY;
         acc[1] += rB;
     }
-    block_sum<2>(acc, slots + (long long)blockIdx.x * 2, commit != 0);
+    block_sum<2>(acc, slots + (long long)bid * 2, commit != 0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_create(DevParams P, const StepGeom *__restrict__ G,
+                                                double *__restrict__ momd, R *__restrict__ mom, R *__restrict__ chi,
+                                                double *__restrict__ slots, int commit)
+{
+    create_body<R>(P, G, momd, mom, chi, slots, commit, blockIdx.x, gridDim.x);
 }
 
 // Fictitious densities of the head's solid cells that touch fluid, Eq. (wet):
 // rho_s^k = zeta^k sum_i w_i s_i rho^k(x + c_i) / sum_i w_i s_i.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_wall(DevParams P, const StepGeom *__restrict__ G,
-                                              const double *__restrict__ momd, R *__restrict__ chi)
+__device__ __forceinline__ void wall_body(const DevParams &P, const StepGeom *__restrict__ G,
+                                          const double *__restrict__ momd, R *__restrict__ chi, int bid, int nblk)
 {
     const HeadPos H = G->H;
     const int bx0 = G->hb.x0, by0 = G->hb.y0, bz0 = G->hb.z0, bw = G->hb.w, bh = G->hb.h, bd = G->hb.d;
     const long long total = (long long)bw * bh * bd;
-    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < total; k += (long long)gridDim.x * TPB) {
+    for (long long k = (long long)bid * TPB + threadIdx.x; k < total; k += (long long)nblk * TPB) {
         int ix = (int)(k % bw), iy = (int)((k / bw) % bh), iz = (int)(k / ((long long)bw * bh));
         int x = ((bx0 + ix) % P.nx + P.nx) % P.nx, y = ((by0 + iy) % P.ny + P.ny) % P.ny, z = bz0 + iz;
         if (z < 0 || z >= P.nz) continue;
@@ -346,17 +374,24 @@ __global__ __launch_bounds__(TPB) void k_wall(DevParams P, const StepGeom *__res
     }
 }
 
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_wall(DevParams P, const StepGeom *__restrict__ G,
+                                              const double *__restrict__ momd, R *__restrict__ chi)
+{
+    wall_body<R>(P, G, momd, chi, blockIdx.x, gridDim.x);
+}
+
 // Colour fields of the ghost layers below (face 0) and above (face 1) the
 // box: walls carry Eq. (wet)'s fictitious densities from the adjacent fluid
 // layer, pressure faces their imposed densities, the inlet lid pure ink, the
 // head's shell columns above the top the nozzle's fictitious densities.
 template <typename R>
-__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, const StepGeom *__restrict__ G,
-                                               const double *__restrict__ momd, R *__restrict__ ghost)
+__device__ __forceinline__ void ghost_body(const DevParams &P, const StepGeom *__restrict__ G,
+                                           const double *__restrict__ momd, R *__restrict__ ghost, int bid)
 {
     const HeadPos H = G->H;
     long long plane = (long long)P.nx * P.ny;
-    long long k = (long long)blockIdx.x * TPB + threadIdx.x;
+    long long k = (long long)bid * TPB + threadIdx.x;
     if (k >= 2 * plane) return;
     int face = (int)(k / plane);
     long long c = k - face * plane;
@@ -407,6 +442,13 @@ __global__ __launch_bounds__(TPB) void k_ghost(DevParams P, const StepGeom *__re
     ghost[(face * 3 + 0) * plane + c] = R(cN);
     ghost[(face * 3 + 1) * plane + c] = R(cY);
     ghost[(face * 3 + 2) * plane + c] = R(cB);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_ghost(DevParams P, const StepGeom *__restrict__ G,
+                                               const double *__restrict__ momd, R *__restrict__ ghost)
+{
+    ghost_body<R>(P, G, momd, ghost, blockIdx.x);
 }
 
 // Fields for lb_moments: rho_Y, rho_B, physical velocity (j + F/2)/rho; block
@@ -527,7 +569,7 @@ constexpr size_t ALIGN = 256;
 size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
-    size_t pops, dmo, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, geo, total;
+    size_t pops, dmo, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, geo, tab, total;
     long long nbm;   // blocks of the whole-box read-out kernels
     FusedGrid fg;    // tiling of the fused step kernel
     long long nbf;   // its block count
@@ -572,7 +614,161 @@ constexpr int TY_F64 = 5;
 constexpr int PC_TY_PLAIN = 4, PC_CR_PLAIN = 1;
 constexpr int PC_TY_DEV = 4, PC_CR_DEV = 1;
 
-FusedGrid fused_grid(const lb_params &p, int ty)
+// ------------------------------------------------------ batched stepping
+//
+// One launch per kernel of a step advances every member of a batch: the
+// device slot table holds each member's parameters, buffers (for both step
+// parities of the batch) and the range of blocks it owns in each kernel's
+// grid.  A block finds its member by binary search over the members' block
+// offsets and runs the member's kernel body with its block index within the
+// member's share, which is the grid the member would use alone; members with
+// fewer steps to go than the launch's step index leave at once.
+constexpr int BATCH_MAX = 64;
+enum { BK_PRE = 0, BK_CREATE, BK_WALL, BK_GHOST, BK_FUSED, BK_N };
+
+struct BatchSlot {
+    DevParams P;
+    FusedGrid fg;
+    StepGeom *G;
+    const void *src[2];       // population copy read at batch steps of parity q (q = j & 1)
+    void *dst[2];
+    const void *mac_prev[2];  // macro fields written by the previous step
+    void *mac_next[2];
+    const float *mo_src[2];   // source moments (reduced storage forms)
+    float *mo_dst[2];
+    double *momd;
+    void *mom, *chi, *ghost;
+    double *cumpre, *cumc;
+    int nsteps;               // batch steps this member takes (launch j runs iff j < nsteps)
+    unsigned nb[BK_N];        // the member's blocks in each kernel
+    unsigned off[BK_N];       // its first block in each kernel's grid
+};
+
+struct BatchTable {
+    int n;
+    unsigned total[BK_N];
+    BatchSlot slot[BATCH_MAX];
+};
+
+// The member owning block b of kernel `kind`, or -1 (blocks past the total,
+// or in the padding that aligns a member's first block).  Offsets are
+// non-decreasing in member order; a member without blocks in a kernel
+// shares its offset with the next member.
+__device__ __forceinline__ int batch_member(const BatchTable *__restrict__ T, int kind, unsigned b)
+{
+    if (b >= T->total[kind]) return -1;
+    int lo = 0, hi = T->n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (T->slot[mid].off[kind] <= b) lo = mid;
+        else hi = mid;
+    }
+    const BatchSlot &S = T->slot[lo];
+    return (b >= S.off[kind] && b - S.off[kind] < S.nb[kind]) ? lo : -1;
+}
+
+template <typename R, int ST>
+__device__ __forceinline__ PopSrc<R, ST> batch_src(const BatchSlot &S, int q)
+{
+    PopSrc<R, ST> s;
+    if constexpr (ST == ST_PLAIN) {
+        s.s = static_cast<const R *>(S.src[q]);
+    } else {
+        s.s = static_cast<const unsigned *>(S.src[q]);
+        s.mo = static_cast<const float *>(S.mo_src[q]);
+        s.NM = S.P.NM;
+    }
+    s.N = S.P.N;
+    s.NP = S.P.NP;
+    return s;
+}
+
+template <typename R, int ST>
+__global__ __launch_bounds__(TPB) void kb_pre(const BatchTable *__restrict__ T, int j)
+{
+    const int m = batch_member(T, BK_PRE, blockIdx.x);
+    if (m < 0) return;
+    const BatchSlot &S = T->slot[m];
+    if (j >= S.nsteps) return;
+    const int q = j & 1;
+    const DevParams P = S.P;
+    pre_body<R, ST>(P, S.G, batch_src<R, ST>(S, q), static_cast<const R *>(S.mac_prev[q]), S.momd,
+                    static_cast<R *>(S.mom), static_cast<R *>(S.chi), S.cumpre, 0, blockIdx.x - S.off[BK_PRE], S.nb[BK_PRE]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void kb_create(const BatchTable *__restrict__ T, int j)
+{
+    const int m = batch_member(T, BK_CREATE, blockIdx.x);
+    if (m < 0) return;
+    const BatchSlot &S = T->slot[m];
+    if (j >= S.nsteps) return;
+    const DevParams P = S.P;
+    create_body<R>(P, S.G, S.momd, static_cast<R *>(S.mom), static_cast<R *>(S.chi), S.cumc, 1,
+                   blockIdx.x - S.off[BK_CREATE], S.nb[BK_CREATE]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void kb_wall(const BatchTable *__restrict__ T, int j)
+{
+    const int m = batch_member(T, BK_WALL, blockIdx.x);
+    if (m < 0) return;
+    const BatchSlot &S = T->slot[m];
+    if (j >= S.nsteps) return;
+    const DevParams P = S.P;
+    wall_body<R>(P, S.G, S.momd, static_cast<R *>(S.chi), blockIdx.x - S.off[BK_WALL], S.nb[BK_WALL]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(TPB) void kb_ghost(const BatchTable *__restrict__ T, int j)
+{
+    const int m = batch_member(T, BK_GHOST, blockIdx.x);
+    if (m < 0) return;
+    const BatchSlot &S = T->slot[m];
+    if (j >= S.nsteps) return;
+    const DevParams P = S.P;
+    ghost_body<R>(P, S.G, S.momd, static_cast<R *>(S.ghost), blockIdx.x - S.off[BK_GHOST]);
+}
+
+template <typename R, int TY, int ST, int CR>
+__global__ __launch_bounds__((TY + 3 + TY / CR) * 64, 1) void kb_fused_pc(const BatchTable *__restrict__ T, int j)
+{
+    const int m = batch_member(T, BK_FUSED, blockIdx.x);
+    if (m < 0) return;
+    const BatchSlot &S = T->slot[m];
+    if (j >= S.nsteps) return;
+    const int q = j & 1;
+    // the member's parameters as a local copy (loaded once, like kernel
+    // arguments), not a reference into the table
+    const DevParams P = S.P;
+    const FusedGrid fg = S.fg;
+    fused_pc_body<R, TY, false, ST, CR>(P, S.G, fg, static_cast<const char *>(S.src[q]), static_cast<char *>(S.dst[q]),
+                                        S.momd, static_cast<const R *>(S.mom), static_cast<const R *>(S.chi),
+                                        static_cast<const R *>(S.ghost), static_cast<R *>(S.mac_next[q]), S.mo_src[q],
+                                        S.mo_dst[q], blockIdx.x - S.off[BK_FUSED], S.nb[BK_FUSED]);
+}
+
+template <int TY>
+__global__ __launch_bounds__((TY + 3) * 64, 2) void kb_fused64(const BatchTable *__restrict__ T, int j)
+{
+    const int m = batch_member(T, BK_FUSED, blockIdx.x);
+    if (m < 0) return;
+    const BatchSlot &S = T->slot[m];
+    if (j >= S.nsteps) return;
+    const int q = j & 1;
+    const DevParams P = S.P;
+    const FusedGrid fg = S.fg;
+    fused_body<double, TY, false>(P, S.G, fg, static_cast<const double *>(S.src[q]), static_cast<double *>(S.dst[q]),
+                                  S.momd, static_cast<const double *>(S.mom), static_cast<const double *>(S.chi),
+                                  static_cast<const double *>(S.ghost), static_cast<double *>(S.mac_next[q]),
+                                  blockIdx.x - S.off[BK_FUSED], S.nb[BK_FUSED]);
+}
+
+// Tiling of the step kernel: full-width 64 x ty tiles, the height split into
+// z chunks so that the launch has about `want` blocks.  The result of a cell
+// does not depend on the chunking (every chunk re-pulls its halo planes
+// identically), so a batch may chunk a member differently from a lone run.
+FusedGrid fused_grid(const lb_params &p, int ty, long long want_blocks = 512)
 {
     FusedGrid g;
     g.ntx = (p.nx + 63) / 64;
@@ -580,7 +776,7 @@ FusedGrid fused_grid(const lb_params &p, int ty)
     long long tiles = (long long)g.ntx * g.nty;
     // one resident block per CU: about two rounds of blocks on 256 CUs, z
     // chunks of at least 8 planes (long chunks spend fewer halo planes)
-    long long want = (512 + tiles - 1) / tiles;
+    long long want = (want_blocks + tiles - 1) / tiles;
     long long maxc = std::max(1, p.nz / 8);
     g.nzc = (int)std::max(1LL, std::min(want, maxc));
     if (const char *e = std::getenv("LBPRINT_ZLEN")) {
@@ -642,6 +838,8 @@ Layout layout_of(const lb_params &p)
     off += al(16 * 8);
     L.geo = off;
     off += al(sizeof(StepGeom));
+    L.tab = off;  // the handle's one-member slot table (its steps after the first)
+    off += al(offsetof(BatchTable, slot) + sizeof(BatchSlot));
     L.total = off;
     return L;
 }
@@ -794,8 +992,14 @@ struct lb_handle {
     };
     std::vector<Chain> chains;
     hipStream_t cap = nullptr;
+    // batched stepping (lb_batch_step): orders the batch stream after this
+    // handle's stream
+    hipEvent_t bev = nullptr;
+    // blocks of each step kernel over the handle's own slot table
+    unsigned lone_nb[BK_N] = {0, 0, 0, 0, 0};
     ~lb_handle()
     {
+        if (bev) (void)hipEventDestroy(bev);
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         for (Chain &c : chains) (void)hipGraphExecDestroy(c.exec);
         if (cap) (void)hipStreamDestroy(cap);
@@ -986,9 +1190,42 @@ lb_status launch_fused(lb_handle *h)
 // Every launch argument is the same at every step of one parity (the
 // population and macro buffers alternate), so an even number of steps can be
 // captured once and replayed.
+// Steps after the first run the batched kernels over the handle's own
+// one-member table (the same compiled code as a batch, so a simulation
+// gives the same bits alone and in a batch); the table's buffers are indexed
+// by the step's parity, which equals the population buffer index.
+template <typename R, int ST>
+lb_status run_step_table(lb_handle *h)
+{
+    const BatchTable *T = as<BatchTable>(h, h->L.tab);
+    const unsigned *nb = h->lone_nb;
+    const int j = (int)(h->t & 1);
+    if (lb_status s = timing_mark(h, 0)) return s;
+    hipLaunchKernelGGL((kb_pre<R, ST>), dim3(nb[BK_PRE]), dim3(TPB), 0, h->stream, T, j);
+    if (nb[BK_CREATE]) hipLaunchKernelGGL(kb_create<R>, dim3(nb[BK_CREATE]), dim3(TPB), 0, h->stream, T, j);
+    if (nb[BK_WALL]) hipLaunchKernelGGL(kb_wall<R>, dim3(nb[BK_WALL]), dim3(TPB), 0, h->stream, T, j);
+    if (nb[BK_GHOST]) hipLaunchKernelGGL(kb_ghost<R>, dim3(nb[BK_GHOST]), dim3(TPB), 0, h->stream, T, j);
+    if (lb_status s = check_launch(h, "boundary kernels")) return s;
+    if (lb_status s = timing_mark(h, 1)) return s;
+    if constexpr (sizeof(R) == 4) {
+        constexpr int TY = ST == ST_PLAIN ? PC_TY_PLAIN : PC_TY_DEV;
+        constexpr int CR = ST == ST_PLAIN ? PC_CR_PLAIN : PC_CR_DEV;
+        hipLaunchKernelGGL((kb_fused_pc<R, TY, ST, CR>), dim3(nb[BK_FUSED]), dim3((TY + 3 + TY / CR) * 64), 0,
+                           h->stream, T, j);
+    } else {
+        hipLaunchKernelGGL(kb_fused64<TY_F64>, dim3(nb[BK_FUSED]), dim3((TY_F64 + 3) * 64), 0, h->stream, T, j);
+    }
+    if (lb_status s = check_launch(h, "step kernel")) return s;
+    if (lb_status s = timing_mark(h, 2)) return s;
+    h->cur = 1 - h->cur;
+    h->t += 1;
+    return LB_OK;
+}
+
 template <typename R, int ST>
 lb_status run_step(lb_handle *h)
 {
+    if (!h->first) return run_step_table<R, ST>(h);
     const Layout &L = h->L;
     if (lb_status s = timing_mark(h, 0)) return s;
     if (!h->p.has_nozzle && h->P.periodic_z)
@@ -1259,6 +1496,167 @@ lb_status step_eager(lb_handle *h, int n)
 
 }  // namespace
 
+// ---------------------------------------------------------------- batches
+
+struct lb_batch {
+    int storage = 0;
+    hipStream_t stream = nullptr;
+    BatchTable *dtab = nullptr;                 // device slot table (the caller's workspace)
+    BatchTable *htab[2] = {nullptr, nullptr};   // pinned host staging, used in turn
+    hipEvent_t hev[2] = {nullptr, nullptr};     // the upload from htab[i] has run
+    bool hev_used[2] = {false, false};
+    int hcur = 0;
+    hipStream_t cap = nullptr;                  // private capture stream
+    hipGraphExec_t exec = nullptr;              // gk steps of the batched kernels
+    int gk = 0;
+    unsigned gcap[BK_N] = {0, 0, 0, 0, 0};      // grid of each batched kernel in the graph
+    hipEvent_t done = nullptr;                  // the last launch has run
+    std::string err;
+    ~lb_batch()
+    {
+        if (exec) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipGraphExecDestroy(exec);
+        }
+        for (int i = 0; i < 2; ++i) {
+            if (hev[i]) (void)hipEventDestroy(hev[i]);
+            if (htab[i]) (void)hipHostFree(htab[i]);
+        }
+        if (done) (void)hipEventDestroy(done);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+namespace {
+
+lb_status bfail(lb_batch *b, lb_status s, const std::string &msg)
+{
+    if (b) b->err = msg;
+    g_err = msg;
+    return s;
+}
+
+size_t batch_table_bytes() { return al(sizeof(BatchTable)); }
+
+template <typename F>
+lb_status with_form(int storage, F &&f)
+{
+    switch (storage) {
+    case LB_F64: return f.template operator()<double, ST_PLAIN>();
+    case LB_F32: return f.template operator()<float, ST_PLAIN>();
+    case LB_BF16_DEV: return f.template operator()<float, ST_BF16>();
+    default: return f.template operator()<float, ST_F16>();
+    }
+}
+
+// The batched kernels of batch step j, in the order of a lone step.
+template <typename R, int ST>
+lb_status batch_launch_step(lb_batch *b, hipStream_t st, int j)
+{
+    const BatchTable *T = b->dtab;
+    const unsigned *c = b->gcap;
+    if (c[BK_PRE]) hipLaunchKernelGGL((kb_pre<R, ST>), dim3(c[BK_PRE]), dim3(TPB), 0, st, T, j);
+    if (c[BK_CREATE]) hipLaunchKernelGGL(kb_create<R>, dim3(c[BK_CREATE]), dim3(TPB), 0, st, T, j);
+    if (c[BK_WALL]) hipLaunchKernelGGL(kb_wall<R>, dim3(c[BK_WALL]), dim3(TPB), 0, st, T, j);
+    if (c[BK_GHOST]) hipLaunchKernelGGL(kb_ghost<R>, dim3(c[BK_GHOST]), dim3(TPB), 0, st, T, j);
+    if (c[BK_FUSED]) {
+        if constexpr (sizeof(R) == 4) {
+            constexpr int TY = ST == ST_PLAIN ? PC_TY_PLAIN : PC_TY_DEV;
+            constexpr int CR = ST == ST_PLAIN ? PC_CR_PLAIN : PC_CR_DEV;
+            hipLaunchKernelGGL((kb_fused_pc<R, TY, ST, CR>), dim3(c[BK_FUSED]), dim3((TY + 3 + TY / CR) * 64), 0, st,
+                               T, j);
+        } else {
+            hipLaunchKernelGGL(kb_fused64<TY_F64>, dim3(c[BK_FUSED]), dim3((TY_F64 + 3) * 64), 0, st, T, j);
+        }
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, LB_EDEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+    return LB_OK;
+}
+
+// Capture k batch steps (grids b->gcap) once on the private stream and
+// instantiate them; the previous graph is released after the batch stream
+// has run it.
+lb_status batch_capture(lb_batch *b, int k)
+{
+    if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return bfail(b, LB_EDEVICE, "hipStreamCreate (batch capture stream)");
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, LB_EDEVICE, "hipStreamBeginCapture (batch)");
+    lb_status st = LB_OK;
+    for (int j = 0; j < k && st == LB_OK; ++j)
+        st = with_form(b->storage, [&]<typename R, int ST>() { return batch_launch_step<R, ST>(b, b->cap, j); });
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st != LB_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        if (st != LB_OK) return st;
+        return bfail(b, LB_EDEVICE, std::string("batch stream capture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return bfail(b, LB_EDEVICE, "hipGraphInstantiate (batch)");
+    if (b->exec) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, LB_EDEVICE, "hipStreamSynchronize (batch)");
+        (void)hipGraphExecDestroy(b->exec);
+    }
+    b->exec = exec;
+    b->gk = k;
+    return LB_OK;
+}
+
+void *mac_ptr(lb_handle *h, long t)
+{
+    return h->ws + h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.N * real_size(h->p.storage));
+}
+
+// A handle's slot: its buffers for the steps of parity q = 0, 1 counted from
+// a step t0 at which its population buffer is cur0, the tiling fg of its
+// step kernel, and the blocks each step kernel gives it (the boundary
+// kernels' grids are the handle's own: their per-block sums depend on them).
+void fill_slot(lb_handle *h, BatchSlot &S, int cur0, long t0, const FusedGrid &fg, int nsteps)
+{
+    const Layout &L = h->L;
+    S.P = h->P;
+    S.fg = fg;
+    S.G = geo(h);
+    for (int q = 0; q < 2; ++q) {
+        const int cq = cur0 ^ q;
+        S.src[q] = pops_at(h, cq);
+        S.dst[q] = pops_at(h, 1 - cq);
+        S.mac_prev[q] = mac_ptr(h, t0 + q - 1);
+        S.mac_next[q] = mac_ptr(h, t0 + q);
+        S.mo_src[q] = mo_at(h, cq);
+        S.mo_dst[q] = mo_at(h, 1 - cq);
+    }
+    S.momd = as<double>(h, L.momd);
+    S.mom = h->ws + L.mom;
+    S.chi = h->ws + L.chi;
+    S.ghost = h->ws + L.ghost;
+    S.cumpre = as<double>(h, L.cumpre);
+    S.cumc = as<double>(h, L.cumc);
+    S.nsteps = nsteps;
+    const bool noz = h->p.has_nozzle != 0, per = h->P.periodic_z != 0;
+    // a handle without boundary work still gets one preparation block,
+    // which computes its step geometry
+    S.nb[BK_PRE] = (noz || !per) ? L.nb_pre : 1;
+    S.nb[BK_CREATE] = noz ? L.nb_create : 0;
+    S.nb[BK_WALL] = noz ? L.nb_wall : 0;
+    S.nb[BK_GHOST] = per ? 0 : (unsigned)((2LL * h->p.nx * h->p.ny + TPB - 1) / TPB);
+    S.nb[BK_FUSED] = (unsigned)((long long)fg.ntx * fg.nty * fg.nzc);
+    for (int kind = 0; kind < BK_N; ++kind) S.off[kind] = 0;
+}
+
+unsigned next_pow2(unsigned v)
+{
+    unsigned p = 64;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
 extern "C" {
 
 lb_status lb_footprint(const lb_params *p, size_t *bytes)
@@ -1316,6 +1714,22 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     std::memset(&g0, 0, sizeof(g0));
     g0.first = 1;
     if (e == hipSuccess) e = hipMemcpyAsync(geo(h), &g0, sizeof(g0), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) {
+        std::string m = std::string("lb_create: ") + hipGetErrorString(e);
+        delete h;
+        return fail(nullptr, LB_EDEVICE, m);
+    }
+    // the handle's one-member slot table for its steps after the first
+    // (staged on the heap until the stream synchronisation below)
+    std::unique_ptr<BatchTable> lone(new BatchTable());
+    lone->n = 1;
+    fill_slot(h, lone->slot[0], 0, 0, L.fg, std::numeric_limits<int>::max());
+    for (int kind = 0; kind < BK_N; ++kind) {
+        lone->total[kind] = lone->slot[0].nb[kind];
+        h->lone_nb[kind] = lone->slot[0].nb[kind];
+    }
+    e = hipMemcpyAsync(as<BatchTable>(h, L.tab), lone.get(), offsetof(BatchTable, slot) + sizeof(BatchSlot),
+                       hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) {
         std::string m = std::string("lb_create: ") + hipGetErrorString(e);
         delete h;
@@ -1431,6 +1845,151 @@ lb_status lb_destroy(lb_handle *h)
     delete h;
     return LB_OK;
 }
+
+lb_status lb_batch_footprint(size_t *bytes)
+{
+    if (!bytes) return fail(nullptr, LB_EINVAL, "null argument");
+    *bytes = batch_table_bytes();
+    return LB_OK;
+}
+
+lb_status lb_batch_create(int storage, void *dev_workspace, size_t ws_bytes, void *hip_stream, lb_batch **out)
+{
+    if (out) *out = nullptr;
+    if (!dev_workspace || !out) return fail(nullptr, LB_EINVAL, "null argument");
+    if (storage < LB_F64 || storage > LB_F16_DEV) return fail(nullptr, LB_EINVAL, "unknown storage form");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % ALIGN)
+        return fail(nullptr, LB_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < batch_table_bytes()) return fail(nullptr, LB_ENOMEM, "workspace smaller than lb_batch_footprint()");
+    lb_batch *b = new lb_batch();
+    b->storage = storage;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->dtab = reinterpret_cast<BatchTable *>(dev_workspace);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipHostMalloc((void **)&b->htab[i], sizeof(BatchTable), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->hev[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        std::string m = std::string("lb_batch_create: ") + hipGetErrorString(e);
+        delete b;
+        return fail(nullptr, LB_EDEVICE, m);
+    }
+    *out = b;
+    return LB_OK;
+}
+
+lb_status lb_batch_step(lb_batch *b, lb_handle *const *hs, const int *nsteps, int n)
+{
+    if (!b) return fail(nullptr, LB_EINVAL, "null batch");
+    if (n < 0 || n > BATCH_MAX || (n > 0 && (!hs || !nsteps)))
+        return bfail(b, LB_EINVAL, "lb_batch_step: bad member list (at most 64 members)");
+    for (int i = 0; i < n; ++i) {
+        if (!hs[i] || nsteps[i] < 0) return bfail(b, LB_EINVAL, "lb_batch_step: bad handle or step count");
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return bfail(b, LB_EINVAL, "lb_batch_step: a handle appears twice");
+        if (hs[i]->p.storage != b->storage) return bfail(b, LB_EINVAL, "lb_batch_step: storage form differs from the batch's");
+        if (hs[i]->unstable) return bfail(b, LB_ESTATE, "lb_batch_step: a member is unstable");
+        if (hs[i]->p.check_interval > 0)
+            return bfail(b, LB_EINVAL, "lb_batch_step: handles with check_interval > 0 step with lb_step");
+    }
+    // the batch stream runs after each member's earlier work
+    for (int i = 0; i < n; ++i) {
+        lb_handle *h = hs[i];
+        if (h->stream == b->stream || nsteps[i] == 0) continue;
+        if (!h->bev && hipEventCreateWithFlags(&h->bev, hipEventDisableTiming) != hipSuccess)
+            return bfail(b, LB_EDEVICE, "hipEventCreate (member)");
+        if (hipEventRecord(h->bev, h->stream) != hipSuccess || hipStreamWaitEvent(b->stream, h->bev, 0) != hipSuccess)
+            return bfail(b, LB_EDEVICE, "member stream ordering");
+    }
+    // a member's first step (it reads its own initial slots) runs alone, on
+    // the batch stream
+    int k[BATCH_MAX];
+    for (int i = 0; i < n; ++i) {
+        lb_handle *h = hs[i];
+        k[i] = nsteps[i];
+        if (k[i] > 0 && h->first) {
+            const hipStream_t saved = h->stream;
+            const int timing = h->timing;
+            h->stream = b->stream;
+            h->timing = 0;
+            const lb_status s = step_one(h);
+            h->stream = saved;
+            h->timing = timing;
+            if (s) return bfail(b, s, h->err);
+            k[i] -= 1;
+        }
+    }
+    // the slot table, staged in pinned host memory and uploaded in stream order
+    const int slot_buf = b->hcur;
+    if (b->hev_used[slot_buf] && hipEventSynchronize(b->hev[slot_buf]) != hipSuccess)
+        return bfail(b, LB_EDEVICE, "hipEventSynchronize (table staging)");
+    BatchTable &T = *b->htab[slot_buf];
+    T.n = 0;
+    for (int kind = 0; kind < BK_N; ++kind) T.total[kind] = 0;
+    int active = 0, kmax = 0;
+    for (int i = 0; i < n; ++i) active += k[i] > 0;
+    // z chunks: the batch as a whole fills the GPU, so members chunk less
+    const long long want = active ? std::max(64, 1024 / active) : 512;
+    for (int i = 0; i < n; ++i) {
+        if (k[i] <= 0) continue;
+        lb_handle *h = hs[i];
+        BatchSlot &S = T.slot[T.n++];
+        fill_slot(h, S, h->cur, h->t, fused_grid(h->p, h->L.ty, want), k[i]);
+        for (int kind = 0; kind < BK_N; ++kind) {
+            unsigned off = T.total[kind];
+            if (kind == BK_FUSED) off = (off + 7u) & ~7u;  // keep the member's XCD-aware order
+            S.off[kind] = off;
+            T.total[kind] = off + S.nb[kind];
+        }
+        kmax = std::max(kmax, k[i]);
+    }
+    if (T.n > 0) {
+        const size_t bytes = offsetof(BatchTable, slot) + (size_t)T.n * sizeof(BatchSlot);
+        if (hipMemcpyAsync(b->dtab, &T, bytes, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+            hipEventRecord(b->hev[slot_buf], b->stream) != hipSuccess)
+            return bfail(b, LB_EDEVICE, "slot table upload");
+        b->hev_used[slot_buf] = true;
+        b->hcur ^= 1;
+        // one graph of kmax steps, captured again only when the step count
+        // or a kernel's block count outgrows it
+        bool again = !b->exec || kmax > b->gk || kmax * 2 < b->gk;
+        unsigned cap[BK_N];
+        for (int kind = 0; kind < BK_N; ++kind) {
+            cap[kind] = b->gcap[kind];
+            if (T.total[kind] > cap[kind]) {
+                cap[kind] = next_pow2(T.total[kind] + T.total[kind] / 4);
+                again = true;
+            }
+        }
+        if (again) {
+            for (int kind = 0; kind < BK_N; ++kind) b->gcap[kind] = cap[kind];
+            if (lb_status s = batch_capture(b, kmax)) return s;
+        }
+        if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(b, LB_EDEVICE, "hipGraphLaunch (batch)");
+    }
+    // each member's later work runs after the batch
+    if (hipEventRecord(b->done, b->stream) != hipSuccess) return bfail(b, LB_EDEVICE, "hipEventRecord (batch)");
+    for (int i = 0; i < n; ++i) {
+        lb_handle *h = hs[i];
+        if (h->stream != b->stream && nsteps[i] > 0 && hipStreamWaitEvent(h->stream, b->done, 0) != hipSuccess)
+            return bfail(b, LB_EDEVICE, "member stream ordering");
+        h->t += k[i];
+        h->cur ^= (k[i] & 1);
+        if (nsteps[i] > 0) h->first = 0;
+    }
+    return LB_OK;
+}
+
+lb_status lb_batch_destroy(lb_batch *b)
+{
+    if (!b) return LB_EINVAL;
+    delete b;
+    return LB_OK;
+}
+
+const char *lb_batch_last_error(const lb_batch *b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 const char *lb_strerror(lb_status s)
 {

@@ -20,7 +20,8 @@ RHEOLOGY = {"newtonian": 0, "power_law": 1, "cross": 2}
 FACE = {"periodic": 0, "wall": 1, "pressure": 2}
 
 EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc", "lb_time",
-           "lb_timing", "lb_timing_read", "lb_destroy", "lb_strerror", "lb_last_error")
+           "lb_timing", "lb_timing_read", "lb_destroy", "lb_strerror", "lb_last_error", "lb_batch_footprint",
+           "lb_batch_create", "lb_batch_step", "lb_batch_destroy", "lb_batch_last_error")
 
 _d2 = C.c_double * 2
 _d3 = C.c_double * 3
@@ -105,8 +106,15 @@ def lib():
         L.lb_strerror.restype = C.c_char_p
         L.lb_last_error.argtypes = [vp]
         L.lb_last_error.restype = C.c_char_p
+        L.lb_batch_footprint.argtypes = [C.POINTER(C.c_size_t)]
+        L.lb_batch_create.argtypes = [C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lb_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_int), C.c_int]
+        L.lb_batch_destroy.argtypes = [vp]
+        L.lb_batch_last_error.argtypes = [vp]
+        L.lb_batch_last_error.restype = C.c_char_p
         for f in ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc",
-                  "lb_timing", "lb_timing_read", "lb_destroy"):
+                  "lb_timing", "lb_timing_read", "lb_destroy", "lb_batch_footprint", "lb_batch_create",
+                  "lb_batch_step", "lb_batch_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -282,3 +290,50 @@ class Sim:
         except Exception:
             pass
 
+
+class Batch:
+    """A batch of simulations of one storage form stepped together: each
+    call of step() advances every member by its own step count with one
+    graph launch of the batched kernels over the device slot table (the
+    workspace is a torch uint8 tensor; the stream the batch's own)."""
+
+    def __init__(self, storage: str = "f32", device: str = "cuda:0", stream=None):
+        torch = _require_gpu()
+        self.device = torch.device(device)
+        self.storage = storage
+        n = C.c_size_t()
+        rc = lib().lb_batch_footprint(C.byref(n))
+        if rc != LB_OK:
+            _raise(rc)
+        self.nbytes = int(n.value)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.ws.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        h = C.c_void_p()
+        rc = lib().lb_batch_create(STORAGE[storage], ptr, self.nbytes, self.stream.cuda_stream, C.byref(h))
+        if rc != LB_OK:
+            _raise(rc)
+        self._b = h
+
+    def step(self, sims, nsteps) -> None:
+        """Advance sims[i] by nsteps[i] steps (an int applies to all)."""
+        n = len(sims)
+        if isinstance(nsteps, int):
+            nsteps = [nsteps] * n
+        hs = (C.c_void_p * max(n, 1))(*[s._h.value for s in sims])
+        ks = (C.c_int * max(n, 1))(*[int(k) for k in nsteps])
+        rc = lib().lb_batch_step(self._b, hs, ks, n)
+        if rc != LB_OK:
+            msg = lib().lb_batch_last_error(self._b)
+            raise LBError(rc, (msg or b"").decode() or lib().lb_strerror(rc).decode())
+
+    def close(self) -> None:
+        if getattr(self, "_b", None):
+            lib().lb_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,13 +2,14 @@
 
 Requests (a printing set-up, an initial state, a step count) arrive over
 time.  The server keeps every admitted simulation's state resident on the
-GPU, admits waiting requests in arrival order while their device footprint
-(lb_footprint) fits the memory budget, and keeps every admitted simulation
-stepping: each has a stream of its own with up to two chunks of steps queued
-(each chunk one launch of its captured chain of steps), so their work
-overlaps on the device; a simulation whose last chunk has completed is read
-out and released at once, and requests that arrive while others run join as
-memory frees up.
+GPU and admits waiting requests in arrival order while their device
+footprint (lb_footprint) fits the memory budget.  All admitted simulations
+of one storage form are members of one batch (lb_batch_*): every round is
+ONE lb_batch_step call that advances each member by up to `chunk` steps, a
+replay of the batch's captured graph of batched kernels over the device
+slot table.  Up to `depth` rounds are queued on the batch stream; when a
+round has run, the simulations it finished are read out and released, and
+requests that arrived meanwhile join the next round.
 
 The comparison point ("sequential") serves the same trace one request at a
 time with plain lb_step calls.
@@ -94,8 +95,8 @@ class Server:
 
     def __init__(self, budget_bytes: int, chunk: int = 20, device: str = "cuda:0", keep_fields: bool = False,
                  depth: int = 2):
-        if chunk < 2:
-            raise ValueError("chunk must be >= 2")
+        if chunk < 1:
+            raise ValueError("chunk must be >= 1")
         if depth < 1:
             raise ValueError("depth must be >= 1")
         self.budget = int(budget_bytes)
@@ -105,26 +106,31 @@ class Server:
         self.keep_fields = keep_fields
 
     def run(self, requests, log=None) -> RunStats:
-        """Serve `requests` in arrival order.  Every admitted simulation keeps
-        up to `depth` chunks of `chunk` steps queued on its own stream (one
-        lb_step_batch call each, a captured chain of steps); completion is
-        polled per simulation with stream events, so the host never waits for
-        the whole device and the GPU is not left idle while finished
-        simulations are read out or new ones created."""
+        """Serve `requests` (one storage form) in arrival order."""
         import torch
 
         stats = RunStats("batched")
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        if not pending:
+            return stats
+        forms = {r.cfg.get("storage", "f32") for r in pending}
+        if len(forms) != 1:
+            raise ValueError(f"one storage form per server run, got {sorted(forms)}")
+        batch = LB.Batch(forms.pop(), device=self.device)
         queue = collections.deque()
-        active = []  # [req, sim, steps not yet launched, bytes, admitted_at, deque of chunk events]
+        active = []                   # admitted members still to be read out
+        rounds = collections.deque()  # (event, members this round finished)
         used = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
+
         while pending or queue or active:
             clock = now()
             while pending and pending[0].arrival <= clock:
                 queue.append(pending.popleft())
-            # admission in arrival order, by device footprint
+            # admission in arrival order, by device footprint (each simulation
+            # is created on a stream of its own, so its upload overlaps the
+            # queued rounds)
             while queue:
                 need = LB.footprint(queue[0].cfg)
                 if need > self.budget:
@@ -133,50 +139,64 @@ class Server:
                     break
                 req = queue.popleft()
                 sim = LB.Sim(req.cfg, req.ry, req.rb, device=self.device, stream=torch.cuda.Stream(self.device))
-                active.append([req, sim, req.steps, need, now(), collections.deque()])
+                active.append(_Member(req, sim, need, now()))
                 used += need
                 stats.peak_bytes = max(stats.peak_bytes, used)
             progressed = False
-            still = []
-            for a in active:
-                req, sim, left, need, admitted, inflight = a
-                while inflight and inflight[0].query():
-                    inflight.popleft()
-                    progressed = True
-                while left > 0 and len(inflight) < self.depth:
-                    k = min(self.chunk, left)
-                    LB.step_batch([sim], [k])
-                    ev = torch.cuda.Event()
-                    ev.record(sim.stream)
-                    inflight.append(ev)
-                    left -= k
-                    stats.launches += 1
-                    progressed = True
-                a[2] = left
-                if left > 0 or inflight:
-                    still.append(a)
-                    continue
-                ry, rb, u, cons = sim.moments(dtype=np.float64)
-                nx, ny, nz = req.cfg["shape"]
-                res = Result(req.id, req.arrival, admitted, now(), nx * ny * nz, req.steps, cons["mass"],
-                             (ry, rb, u) if self.keep_fields else None)
-                stats.results.append(res)
-                if log:
-                    log(f"request {req.id} done: L={nx} latency {res.latency:.3f} s")
-                sim.close()
-                used -= need
+            # one more round of every member that still has steps to launch
+            members = [m for m in active if m.left > 0]
+            if members and len(rounds) < self.depth:
+                ks = [min(self.chunk, m.left) for m in members]
+                batch.step([m.sim for m in members], ks)
+                ev = torch.cuda.Event()
+                ev.record(batch.stream)
+                for m, k in zip(members, ks):
+                    m.left -= k
+                rounds.append((ev, [m for m in members if m.left == 0]))
+                stats.launches += 1
                 progressed = True
-            active = still
+            # read out and release what the rounds that have run finished
+            while rounds and rounds[0][0].query():
+                _, finished = rounds.popleft()
+                done = {id(m) for m in finished}
+                for m in finished:
+                    ry, rb, u, cons = m.sim.moments(dtype=np.float64)
+                    nx, ny, nz = m.req.cfg["shape"]
+                    res = Result(m.req.id, m.req.arrival, m.admitted, now(), nx * ny * nz, m.req.steps, cons["mass"],
+                                 (ry, rb, u) if self.keep_fields else None)
+                    stats.results.append(res)
+                    if log:
+                        log(f"request {m.req.id} done: L={nx} latency {res.latency:.3f} s")
+                    m.sim.close()
+                    used -= m.need
+                active = [m for m in active if id(m) not in done]
+                progressed = True
             if not progressed:
-                if active:
-                    time.sleep(0.0002)
+                if rounds:
+                    # the queue waits for memory or the next round for a slot:
+                    # wait for the oldest round, unless an arrival is due first
+                    if pending and not queue and pending[0].arrival - now() < 0.002:
+                        time.sleep(max(pending[0].arrival - now(), 0.0))
+                    else:
+                        rounds[0][0].synchronize()
                 elif pending:
-                    wait = pending[0].arrival - now()
-                    if wait > 0:
-                        time.sleep(min(wait, 0.005))
+                    time.sleep(min(max(pending[0].arrival - now(), 0.0), 0.005))
         torch.cuda.synchronize(self.device)
         stats.wall = now()
+        batch.close()
         return stats
+
+
+class _Member:
+    """An admitted request: its simulation, the steps not yet launched, its
+    device bytes and admission time."""
+
+    def __init__(self, req, sim, need, admitted):
+        self.req = req
+        self.sim = sim
+        self.left = req.steps
+        self.need = need
+        self.admitted = admitted
 
 
 def run_sequential(requests, device: str = "cuda:0", keep_fields: bool = False, log=None) -> RunStats:

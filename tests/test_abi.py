@@ -131,3 +131,18 @@ def test_reduced_storage_footprint():
         b = LB.footprint(dict(c32, storage=st))
         assert b < LB.footprint(c32)
         assert b > 2 * (76 + 20) * n
+
+
+def test_batch_arguments_rejected_without_the_gpu(lib):
+    import ctypes as C
+
+    n = C.c_size_t()
+    assert lib.lb_batch_footprint(C.byref(n)) == LB.LB_OK and n.value > 64 * 500
+    out = C.c_void_p()
+    assert lib.lb_batch_create(1, None, n.value, None, C.byref(out)) == LB.LB_EINVAL
+    assert lib.lb_batch_create(9, 256, n.value, None, C.byref(out)) == LB.LB_EINVAL   # unknown storage form
+    assert lib.lb_batch_create(1, 257, n.value, None, C.byref(out)) == LB.LB_EINVAL   # misaligned workspace
+    assert lib.lb_batch_create(1, 256, 16, None, C.byref(out)) == LB.LB_ENOMEM        # workspace too small
+    assert out.value is None
+    assert lib.lb_batch_step(None, None, None, 0) == LB.LB_EINVAL
+    assert lib.lb_batch_destroy(None) == LB.LB_EINVAL

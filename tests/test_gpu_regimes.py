@@ -185,8 +185,13 @@ ALPHA_10 = (1.0 - (2.0 / 3.0) / RATIO, 1.0 / 3.0)  # gamma = (1 - alpha_B) / (1 
 def test_density_ratio_10_printing(G, O):
     """Ink ten times as dense as the air (alpha_Y = 0.9333, alpha_B = 1/3,
     rho_Y^0 = 10): unequal phi tables in the equilibria, the anti-bounce-back
-    face and the recolouring, with the moving head and the inlet."""
-    cfg, ry, rb = printing_box(alpha=ALPHA_10, rho0=(RATIO, 1.0), nozzle=dict(lid_rho_y=RATIO))
+    face and the recolouring, with the moving head and the inlet.  Ink and
+    head at 0.01 lattice units per step: the ink's sound speed is only
+    sqrt((1 - alpha_Y)/2) = 0.18 at this ratio, and at the small box's faster
+    speeds (0.02, 0.03) the oracle's own run grows unstable within 900 steps
+    and amplifies rounding long before."""
+    cfg, ry, rb = printing_box(alpha=ALPHA_10, rho0=(RATIO, 1.0),
+                               nozzle=dict(lid_rho_y=RATIO, v=(0.01, 0.005), u_ink=(0.0, 0.0, -0.01)))
     parity(G, O, cfg, ry, rb, (1, 100, 400), "ratio 10 printing")
 
 
@@ -199,10 +204,10 @@ def test_density_ratio_10_droplet(G, O):
     rng = np.random.default_rng(10)
     ry = np.where(ins, RATIO, 0.0) + rng.uniform(0, 1e-3, ins.shape)
     rb = np.where(ins, 0.0, 1.0) + rng.uniform(0, 1e-3, ins.shape)
-    # from rest the two phases' moving populations balance (equal pressures),
-    # so the first steps' velocity is rounding-sized: FP32 is compared once
-    # the spurious currents have developed
-    ref = parity(G, O, cfg, ry, rb, (1, 200, 500), "ratio 10 droplet", fp32_from=200)
+    # FP64 only: a droplet's spurious currents amplify rounding (the FP32
+    # droplet at ratio 1 is bounded by the oracle's own noise response in
+    # test_gpu_parity); FP32 at this ratio is checked on the printing box
+    ref = parity(G, O, cfg, ry, rb, (1, 200, 500), "ratio 10 droplet", storages=("f64",))
     c = ref[500][3]
     assert abs(c["mass"][0] - ry.sum()) < 1e-10 * ry.sum()
 
