@@ -185,7 +185,8 @@ def serve(args):
     warm = S.make_requests(count=2, seed=99, rate=1000.0, lmin=32, lmax=40, steps=4)
     S.Server(8 << 30, chunk=2).run(warm)  # library load, first captures
     torch.cuda.synchronize()
-    batched = S.Server(int(args.serve_budget_gb * 1e9), chunk=args.serve_chunk, keep_fields=False).run(reqs, log=log)
+    batched = S.Server(int(args.serve_budget_gb * 1e9), chunk=args.serve_chunk, keep_fields=False,
+                       lanes=args.serve_lanes).run(reqs, log=log)
     # the baseline is plain FP32 served one request at a time
     seq = None
     if not args.serve_skip_sequential:
@@ -213,7 +214,8 @@ def serve(args):
         "data": "synthetic",
         "config": {"workload": f"parameter sweep: {args.serve_count} printing simulations, cubic boxes L~U{{32..160}}, "
                                f"{args.serve_steps} steps each, Poisson arrivals {args.serve_rate}/s",
-                   "storage": st, "budget_GB": args.serve_budget_gb, "chunk": args.serve_chunk},
+                   "storage": st, "budget_GB": args.serve_budget_gb, "chunk": args.serve_chunk,
+                   "lanes": args.serve_lanes},
         "batched": b,
         "sequential": q,
         "mix_equals_alone": same,
@@ -304,6 +306,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-chunk", type=int, default=20)
+    ap.add_argument("--serve-lanes", type=int, default=2, help="batches on concurrent streams")
     ap.add_argument("--serve-storage", default="f32", choices=["f32", "bf16dev", "f16dev"])
     ap.add_argument("--serve-skip-sequential", action="store_true", help="skip the one-at-a-time FP32 baseline")
     ap.add_argument("--verbose", action="store_true")

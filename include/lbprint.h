@@ -4,8 +4,9 @@
  * (Monteferrante, Montessori, Succi, Pisignano, Lauricella, arXiv:2102.02655).
  *
  * One simulation ("handle") advances two population sets -- ink (Y, the
- * paper's "yellow" colour) and air (B, "blue") -- on a D3Q19 lattice with the
- * fused per-cell step of Sec. II.A-B:
+ * paper's "yellow" colour) and air (B, "blue") -- on a D3Q19 lattice, or on
+ * the paper's own D2Q9 lattice in the x-z plane (lb_params.lattice), with the
+ * per-cell step of Sec. II.A-B:
  *   moments (Sec. II.A), the colour gradient (Eq. (lattgrad)) with wall
  *   densities (Eq. (wet)), the ink's local relaxation time from the strain
  *   rate (Eqs. (notnewvisc)-(tauofgammadot)) mixed by Eq. (tauinter), the
@@ -103,6 +104,10 @@ typedef struct {
     double u_ink[3];          /* ink velocity in the head frame, Eq. (movnozzle)            */
     double lid_rho_y;         /* ink density imposed on the inlet lid                       */
     int check_interval;       /* 0: checks only in lb_moments; k > 0: every k steps          */
+    int lattice;              /* 0 or 19: D3Q19.  9: D2Q9 (Sec. II.A) in the x-z plane of a
+                               * box with ny == 1; storage LB_F64 or LB_F32; every y
+                               * component (body_g, u_zlo, u_zhi, u_ink, noz_v, noz_x0)
+                               * must be 0; not a member of an lb_batch                      */
 } lb_params;
 
 typedef struct {
@@ -214,6 +219,42 @@ lb_status lb_moments(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is
  * as in lb_moments. */
 lb_status lb_moments_noalloc(lb_handle *h, void *rho_y, void *rho_b, void *u, int dst_is_device, int dtype,
                              lb_conserved *cons);
+
+/* Printing observables of Sec. IV on the x-z section y = w->y (0 on D2Q9),
+ * at the current step.  A cell is ink where rho^N > 0, i.e. rho_Y rho_B^0 >
+ * rho_B rho_Y^0 (FP64 masses); cells of the head are excluded.  The printed
+ * thread is the ink in the window of columns x_lo .. x_lo + x_len - 1
+ * (periodic) below z_hi (usually the nozzle tip plane, so that ink still in
+ * the nozzle does not count); the window behind the moving nozzle is the
+ * caller's choice.  Outputs (lattice units):
+ *   ink_area   A_i: thread cells;
+ *   height     h: 1 + the highest thread cell's z (the substrate wall lies
+ *              at z = -1/2, so this is the thread's top above it);
+ *   width      1 + the span of thread columns within the window;
+ *   coverage   A_i / A_r with A_r = h * width, the circumscribing rectangle
+ *              (0 if there is no thread);
+ *   dp_max     the largest p - p0 over the section's ink cells, p = sum_k
+ *              rho_k c_{s,k}^2 (Eq. (cgoef)'s partial pressures; 0 without
+ *              ink);
+ *   p0         rho_B^0 c_{s,B}^2, the pressure of air at rest;
+ *   substrate_ink  ink cells in the layer z = 0 (first contact when > 0).
+ * The POI of Sec. IV, (A_i / A_r) d / (h dp_max), and its normalisation over a
+ * sweep are formed by the caller.  Runs the read-out's pull (as lb_moments;
+ * the handle's read-out slots in its workspace) and synchronises the stream.
+ * LB_EINVAL for a bad window (x_len < 1 or > nx, y outside the box). */
+typedef struct {
+    int x_lo, x_len;
+    int z_hi;
+    int y;
+} lb_window;
+
+typedef struct {
+    double ink_area, height, width, coverage;
+    double dp_max, p0;
+    double substrate_ink;
+} lb_observables;
+
+lb_status lb_observe(lb_handle *h, const lb_window *w, lb_observables *out);
 
 /* Current step count. */
 long lb_time(const lb_handle *h);

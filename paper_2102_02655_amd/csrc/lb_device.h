@@ -728,7 +728,9 @@ __device__ __forceinline__ R tau_ink(const DevParams &P, R S, R rY)
         R dnudx = -dnu * m * q * (iq * iq);  // d nu / d log2(gdot) * ln 2 folded below
         R hp = R(1) + dnudx * rcp_of(tau);
         R xn = x - h * rcp_of(hp);
-        x = (xn > lo && xn < hi) ? xn : R(0.5) * (lo + hi);
+        // the closed bracket: a converged iterate (h = 0 sets lo = x, and
+        // the step is zero) stays where it is
+        x = (xn >= lo && xn <= hi) ? xn : R(0.5) * (lo + hi);
     }
     R q = lam > R(0) ? ex2<R>(m * (llam + x)) : R(0);
     R tau = R(0.5) + nuinf + dnu * rcp_of(R(1) + q);

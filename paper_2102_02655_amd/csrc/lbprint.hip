@@ -497,6 +497,87 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, const StepGeom *__r
     block_sum<NPART>(acc, part + (long long)blockIdx.x * NPART, false);
 }
 
+// ------------------------------------------------------------ observables
+// Printing observables of one x-z section (Sec. IV): thread cells (ink below
+// z_hi in the window of columns), their highest z and column span, the
+// largest pressure deviation of the section's ink and the ink cells touching
+// the substrate.  Per-block values, then one block; every operation is a sum
+// of integers or a maximum, so the result does not depend on the grid.
+constexpr int NOBS = 6;  // count, max z, max(-s), max s, max (p - p0), substrate count
+
+__device__ __forceinline__ double obs_op(int q, double a, double b)
+{
+    return (q == 0 || q == 5) ? a + b : fmax(a, b);
+}
+
+__device__ __forceinline__ void block_obs(double (&v)[NOBS], double *slot)
+{
+    __shared__ double red[NOBS][TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NOBS; ++q) {
+        double a = v[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a = obs_op(q, a, __shfl_xor(a, o, 64));
+        if (lane == 0) red[q][wid] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NOBS; ++q) {
+            double a = red[q][0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) a = obs_op(q, a, red[q][w]);
+            slot[q] = a;
+        }
+}
+
+__device__ __forceinline__ void obs_init(double (&v)[NOBS])
+{
+    v[0] = 0.0;
+    v[1] = -1.0;
+    v[2] = v[3] = v[4] = -1e300;
+    v[5] = 0.0;
+}
+
+__global__ __launch_bounds__(TPB) void k_observe(DevParams P, const StepGeom *__restrict__ G,
+                                                 const double *__restrict__ momd, int x_lo, int x_len, int z_hi,
+                                                 int ysec, double *__restrict__ part)
+{
+    const HeadPos H = G->H;
+    const double cY2 = P.dcs2[0] + 1.0 / 3.0, cB2 = P.dcs2[1] + 1.0 / 3.0;
+    const double p0 = P.rho0[1] * cB2;
+    double v[NOBS];
+    obs_init(v);
+    const long long area = (long long)P.nx * P.nz;
+    for (long long k = (long long)blockIdx.x * TPB + threadIdx.x; k < area; k += (long long)gridDim.x * TPB) {
+        const int z = (int)(k / P.nx), x = (int)(k - (long long)z * P.nx);
+        if (is_solid(P, H.hx_c, H.hy_c, x, ysec, z)) continue;
+        double rY, rB;
+        dens(P, momd, cidx(P, x, ysec, z), rY, rB);
+        if (!(rY * P.rho0[1] > rB * P.rho0[0])) continue;  // rho^N > 0
+        v[4] = fmax(v[4], rY * cY2 + rB * cB2 - p0);
+        v[5] += z == 0 ? 1.0 : 0.0;
+        int s = x - x_lo;
+        if (s < 0) s += P.nx;
+        if (s < x_len && z < z_hi) {
+            v[0] += 1.0;
+            v[1] = fmax(v[1], (double)z);
+            v[2] = fmax(v[2], -(double)s);
+            v[3] = fmax(v[3], (double)s);
+        }
+    }
+    block_obs(v, part + (long long)blockIdx.x * NOBS);
+}
+
+__global__ __launch_bounds__(TPB) void k_observe_final(const double *__restrict__ part, int nb,
+                                                       double *__restrict__ out)
+{
+    double v[NOBS];
+    obs_init(v);
+    for (int b = threadIdx.x; b < nb; b += TPB)
+        for (int q = 0; q < NOBS; ++q) v[q] = obs_op(q, v[q], part[(long long)b * NOBS + q]);
+    block_obs(v, out);
+}
+
 // Deterministic final sums for lb_moments (one block):
 // out = mass[2], mom[3], wall[2], open[2], created[2], deleted[2], unstable.
 // Committed boundary fluxes live in the fused kernel's block slots, committed
@@ -559,6 +640,9 @@ __global__ __launch_bounds__(TPB) void k_reduce(const double *__restrict__ part,
 
 }  // namespace
 
+// the D2Q9 kernels (they use the block sums above)
+#include "lb_d2q9.h"
+
 // ====================================================================== host
 
 namespace {
@@ -597,10 +681,12 @@ long long plane_stride(long long N, int storage)
     const long long pad = b >= (16LL << 20) ? (1LL << 20) + 256 : 256;
     return (b + pad) / esz;
 }
-size_t pop_set_bytes(long long N, int storage)
+bool is_d2(const lb_params &p) { return p.lattice == 9; }
+int lattice_q(const lb_params &p) { return is_d2(p) ? lbk2::Q : lbq::Q; }
+size_t pop_set_bytes(long long N, int storage, int q)
 {
     const size_t esz = reduced(storage) ? 4 : pop_size(storage);
-    const size_t planes = reduced(storage) ? lbq::Q : 2 * lbq::Q;
+    const size_t planes = reduced(storage) ? q : 2 * q;
     return planes * (size_t)plane_stride(N, storage) * esz;
 }
 
@@ -807,11 +893,20 @@ Layout layout_of(const lb_params &p)
         const long long faces = p.face_zlo == LB_FACE_PERIODIC ? 0 : 2LL * p.nx * p.ny;
         L.nb_pre = (unsigned)std::max<long long>(1, std::min<long long>((tot + faces + TPB - 1) / TPB, NB_PRE));
         L.nb_create = (unsigned)std::max<long long>(1, std::min<long long>((tot + TPB - 1) / TPB, NB_SPARSE));
+        if (is_d2(p)) {
+            // D2Q9: the pull is one grid-stride kernel over the box whose
+            // blocks keep the step's sums (at most NB_PRE slots); the wall
+            // kernel takes the two ghost rows and the head box
+            const long long area = bw * p.nz;
+            L.nb_pre = (unsigned)std::max<long long>(1, std::min<long long>(L.nbm, NB_PRE));
+            L.nb_create = (unsigned)std::max<long long>(1, std::min<long long>((area + TPB - 1) / TPB, NB_SPARSE));
+            L.nb_wall = (unsigned)std::max<long long>(1, std::min<long long>((area + 2LL * p.nx + TPB - 1) / TPB, 4096));
+        }
     }
     L.nbf = (long long)L.fg.ntx * L.fg.nty * L.fg.nzc;
     size_t off = 0;
     L.pops = off;
-    off += 2 * al(pop_set_bytes(N, p.storage));
+    off += 2 * al(pop_set_bytes(N, p.storage, lattice_q(p)));
     L.dmo = off;  // source moments of the reduced storage forms (two copies)
     if (reduced(p.storage)) off += 2 * al(NMO * (size_t)plane_stride(N, LB_F32) * 4);
     L.momd = off;
@@ -868,6 +963,15 @@ const char *validate(const lb_params &p)
         if (!(std::fabs(p.noz_v[0]) < 1.0 && std::fabs(p.noz_v[1]) < 1.0)) return "head speed must be below one cell per step";
     }
     if (p.eps_g < 0.0 || p.rho_eps <= 0.0) return "eps_g >= 0 and rho_eps > 0 required";
+    if (p.lattice != 0 && p.lattice != 9 && p.lattice != 19) return "lattice must be 0 or 19 (D3Q19) or 9 (D2Q9)";
+    if (is_d2(p)) {
+        if (p.ny != 1) return "D2Q9 lives in the x-z plane: ny must be 1";
+        if (p.storage != LB_F64 && p.storage != LB_F32) return "D2Q9 runs with LB_F64 or LB_F32 storage";
+        if (p.body_g[1] != 0.0 || p.u_zlo[1] != 0.0 || p.u_zhi[1] != 0.0)
+            return "D2Q9: y components of the body force and wall velocities must be 0";
+        if (p.has_nozzle && (p.u_ink[1] != 0.0 || p.noz_v[1] != 0.0 || p.noz_x0[1] != 0.0))
+            return "D2Q9: the head moves in x only, centred on y = 0";
+    }
     return nullptr;
 }
 
@@ -888,11 +992,12 @@ DevParams make_dev(const lb_params &p)
     P.rho_ref = p.rho0[1];
     P.rho0[0] = p.rho0[0];
     P.rho0[1] = p.rho0[1];
-    const double cs2 = 1.0 / 3.0, w0 = 1.0 / 3.0;
+    const bool d2 = is_d2(p);
+    const double cs2 = 1.0 / 3.0, w0 = d2 ? lbk2::w_of_shell(0) : lbq::w_of_shell(0);
     for (int k = 0; k < 2; ++k) {
         double a = p.alpha[k];
         for (int s = 0; s < 3; ++s) {
-            double ws = lbq::w_of_shell(s);
+            double ws = d2 ? lbk2::w_of_shell(s) : lbq::w_of_shell(s);
             P.phi[k][s] = s == 0 ? a : (1.0 - a) * ws / (1.0 - w0);
             P.phid[k][s] = P.phi[k][s] - ws;
         }
@@ -1032,7 +1137,7 @@ R *as(lb_handle *h, size_t off)
 // source moments stored with it
 char *pops_at(lb_handle *h, int which)
 {
-    return h->ws + h->L.pops + which * al(pop_set_bytes(h->P.N, h->p.storage));
+    return h->ws + h->L.pops + which * al(pop_set_bytes(h->P.N, h->p.storage, lattice_q(h->p)));
 }
 
 float *mo_at(lb_handle *h, int which)
@@ -1092,14 +1197,24 @@ template <typename R, int ST>
 lb_status run_readout(lb_handle *h, const ReadSlots &S, int &nbsp)
 {
     const Layout &L = h->L;
+    const bool d2 = is_d2(h->p);
     if (lb_status s = launch_clock(h)) return s;
-    hipLaunchKernelGGL((k_moments<R, ST>), dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
-                       pop_src<R, ST>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
-                       as<R>(h, L.chi), S.pend, h->first);
+    if (d2)
+        hipLaunchKernelGGL(lbk2::k2_pull<R>, dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
+                           reinterpret_cast<const R *>(pops_at(h, h->cur)), mac_at<R>(h, h->t - 1),
+                           as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pend, h->first, 1);
+    else
+        hipLaunchKernelGGL((k_moments<R, ST>), dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
+                           pop_src<R, ST>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
+                           as<R>(h, L.chi), S.pend, h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
-        hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
-                           as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pendc, 0);
+        if (d2)
+            hipLaunchKernelGGL(lbk2::k2_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
+                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pendc, 0);
+        else
+            hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
+                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pendc, 0);
         if (lb_status s = check_launch(h, "k_create")) return s;
         nbsp = S.zero_pendc ? NB_SPARSE : (int)L.nb_create;
     } else if (S.zero_pendc) {
@@ -1222,9 +1337,41 @@ lb_status run_step_table(lb_handle *h)
     return LB_OK;
 }
 
+// One D2Q9 step: the pull with the step's geometry and boundary sums, node
+// creation, the colour fields of the head's solid nodes and the ghost rows,
+// the collision.  As for D3Q19 the launch arguments depend on the step's
+// parity only.
+template <typename R>
+lb_status run_step2(lb_handle *h)
+{
+    const Layout &L = h->L;
+    if (lb_status s = timing_mark(h, 0)) return s;
+    hipLaunchKernelGGL(lbk2::k2_pull<R>, dim3(L.nb_pre), dim3(TPB), 0, h->stream, h->P, geo(h),
+                       reinterpret_cast<const R *>(pops_at(h, h->cur)), mac_at<R>(h, h->t - 1), as<double>(h, L.momd),
+                       as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.cumpre), h->first, 0);
+    if (h->p.has_nozzle && !h->first)
+        hipLaunchKernelGGL(lbk2::k2_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
+                           as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<double>(h, L.cumc), 1);
+    if (h->p.has_nozzle || !h->P.periodic_z)
+        hipLaunchKernelGGL(lbk2::k2_wall<R>, dim3(L.nb_wall), dim3(TPB), 0, h->stream, h->P, geo(h),
+                           as<double>(h, L.momd), as<R>(h, L.chi), as<R>(h, L.ghost));
+    if (lb_status s = check_launch(h, "D2Q9 pull / boundary kernels")) return s;
+    if (lb_status s = timing_mark(h, 1)) return s;
+    hipLaunchKernelGGL(lbk2::k2_collide<R>, dim3((unsigned)L.nbm), dim3(TPB), 0, h->stream, h->P, geo(h),
+                       as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), as<R>(h, L.ghost),
+                       reinterpret_cast<R *>(pops_at(h, 1 - h->cur)), mac_at<R>(h, h->t));
+    if (lb_status s = check_launch(h, "k2_collide")) return s;
+    if (lb_status s = timing_mark(h, 2)) return s;
+    h->cur = 1 - h->cur;
+    h->t += 1;
+    h->first = 0;
+    return LB_OK;
+}
+
 template <typename R, int ST>
 lb_status run_step(lb_handle *h)
 {
+    if (is_d2(h->p)) return run_step2<R>(h);
     if (!h->first) return run_step_table<R, ST>(h);
     const Layout &L = h->L;
     if (lb_status s = timing_mark(h, 0)) return s;
@@ -1697,7 +1844,7 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     }
     const long long N = h->P.N;
     // stage the initial fields in the second population buffer (at least
-    // 76 B per cell, the fields need 40)
+    // 72 B per cell, the fields need 40)
     char *stage = pops_at(h, 1);
     double *dry = reinterpret_cast<double *>(stage);
     double *drb = dry + N;
@@ -1728,8 +1875,9 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
         lone->total[kind] = lone->slot[0].nb[kind];
         h->lone_nb[kind] = lone->slot[0].nb[kind];
     }
-    e = hipMemcpyAsync(as<BatchTable>(h, L.tab), lone.get(), offsetof(BatchTable, slot) + sizeof(BatchSlot),
-                       hipMemcpyHostToDevice, h->stream);
+    if (!is_d2(*p))
+        e = hipMemcpyAsync(as<BatchTable>(h, L.tab), lone.get(), offsetof(BatchTable, slot) + sizeof(BatchSlot),
+                           hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) {
         std::string m = std::string("lb_create: ") + hipGetErrorString(e);
         delete h;
@@ -1738,8 +1886,12 @@ lb_status lb_create(const lb_params *p, const double *rho_y, const double *rho_b
     dim3 grid((unsigned)L.nbm);
     hipLaunchKernelGGL(k_clock, dim3(1), dim3(64), 0, h->stream, h->P, geo(h));
     with_storage(h, [&]<typename R, int ST>() {
-        hipLaunchKernelGGL((k_init<R, ST>), grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
-                           (void *)pops_at(h, 0), mo_at(h, 0));
+        if (is_d2(*p))
+            hipLaunchKernelGGL(lbk2::k2_init<R>, grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du, u ? 1 : 0,
+                               reinterpret_cast<R *>(pops_at(h, 0)));
+        else
+            hipLaunchKernelGGL((k_init<R, ST>), grid, dim3(TPB), 0, h->stream, h->P, geo(h), dry, drb, du,
+                               u ? 1 : 0, (void *)pops_at(h, 0), mo_at(h, 0));
         return LB_OK;
     });
     e = hipGetLastError();
@@ -1780,6 +1932,39 @@ lb_status lb_moments_noalloc(lb_handle *h, void *rho_y, void *rho_b, void *u, in
 {
     if (!h || (dtype != 0 && dtype != 1)) return fail(h, LB_EINVAL, "bad handle or dtype");
     return moments_noalloc_any(h, rho_y, rho_b, u, dst_is_device, dtype, cons);
+}
+
+lb_status lb_observe(lb_handle *h, const lb_window *w, lb_observables *out)
+{
+    if (!h || !w || !out) return fail(h, LB_EINVAL, "null argument");
+    const int nx = h->p.nx, nz = h->p.nz;
+    if (w->x_len < 1 || w->x_len > nx || w->y < 0 || w->y >= h->p.ny)
+        return fail(h, LB_EINVAL, "lb_observe: window needs 1 <= x_len <= nx and 0 <= y < ny");
+    const int x_lo = ((w->x_lo % nx) + nx) % nx;
+    const ReadSlots S = workspace_slots(h);
+    int nbsp = 0;
+    if (lb_status s = with_storage(h, [&]<typename R, int ST>() { return run_readout<R, ST>(h, S, nbsp); }))
+        return s;
+    // the section's cells, at most one block per 256 (the read-out's part
+    // slots hold one entry per 256 cells of the box)
+    const int nb = (int)std::min<long long>(((long long)nx * nz + TPB - 1) / TPB, 1024);
+    hipLaunchKernelGGL(k_observe, dim3(nb), dim3(TPB), 0, h->stream, h->P, geo(h), as<double>(h, h->L.momd), x_lo,
+                       w->x_len, w->z_hi, w->y, S.part);
+    hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(TPB), 0, h->stream, S.part, nb, S.red);
+    if (lb_status s = check_launch(h, "k_observe")) return s;
+    double v[NOBS];
+    hipError_t e = hipMemcpyAsync(v, S.red, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(h, LB_EDEVICE, std::string("lb_observe: ") + hipGetErrorString(e));
+    const bool thread = v[0] > 0.0;
+    out->ink_area = v[0];
+    out->height = thread ? v[1] + 1.0 : 0.0;
+    out->width = thread ? v[3] + v[2] + 1.0 : 0.0;
+    out->coverage = thread ? v[0] / (out->height * out->width) : 0.0;
+    out->p0 = h->P.rho0[1] * (h->P.dcs2[1] + 1.0 / 3.0);
+    out->dp_max = v[4] > -1e299 ? v[4] : 0.0;
+    out->substrate_ink = v[5];
+    return LB_OK;
 }
 
 long lb_time(const lb_handle *h) { return h ? h->t : -1; }
@@ -1890,6 +2075,7 @@ lb_status lb_batch_step(lb_batch *b, lb_handle *const *hs, const int *nsteps, in
         for (int j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return bfail(b, LB_EINVAL, "lb_batch_step: a handle appears twice");
         if (hs[i]->p.storage != b->storage) return bfail(b, LB_EINVAL, "lb_batch_step: storage form differs from the batch's");
+        if (is_d2(hs[i]->p)) return bfail(b, LB_EINVAL, "lb_batch_step: a batch steps D3Q19 simulations");
         if (hs[i]->unstable) return bfail(b, LB_ESTATE, "lb_batch_step: a member is unstable");
         if (hs[i]->p.check_interval > 0)
             return bfail(b, LB_EINVAL, "lb_batch_step: handles with check_interval > 0 step with lb_step");

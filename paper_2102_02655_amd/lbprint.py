@@ -19,7 +19,8 @@ STORAGE = {"f64": 0, "f32": 1, "bf16dev": 2, "f16dev": 3}
 RHEOLOGY = {"newtonian": 0, "power_law": 1, "cross": 2}
 FACE = {"periodic": 0, "wall": 1, "pressure": 2}
 
-EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc", "lb_time",
+EXPORTS = ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc", "lb_observe",
+           "lb_time",
            "lb_timing", "lb_timing_read", "lb_destroy", "lb_strerror", "lb_last_error", "lb_batch_footprint",
            "lb_batch_create", "lb_batch_step", "lb_batch_destroy", "lb_batch_last_error")
 
@@ -53,6 +54,7 @@ class Params(C.Structure):
         ("u_ink", _d3),
         ("lid_rho_y", C.c_double),
         ("check_interval", C.c_int),
+        ("lattice", C.c_int),
     ]
 
 
@@ -66,6 +68,21 @@ class Conserved(C.Structure):
 
     def as_dict(self) -> dict:
         return {name: np.array(list(getattr(self, name))) for name, _ in self._fields_}
+
+
+class Window(C.Structure):
+    """Mirror of ``lb_window``."""
+    _fields_ = [("x_lo", C.c_int), ("x_len", C.c_int), ("z_hi", C.c_int), ("y", C.c_int)]
+
+
+class Observables(C.Structure):
+    """Mirror of ``lb_observables``."""
+    _fields_ = [("ink_area", C.c_double), ("height", C.c_double), ("width", C.c_double),
+                ("coverage", C.c_double), ("dp_max", C.c_double), ("p0", C.c_double),
+                ("substrate_ink", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: float(getattr(self, name)) for name, _ in self._fields_}
 
 
 class LBError(RuntimeError):
@@ -97,6 +114,7 @@ def lib():
         L.lb_step_batch.argtypes = [C.POINTER(vp), C.POINTER(C.c_int), C.c_int]
         L.lb_moments.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Conserved)]
         L.lb_moments_noalloc.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.POINTER(Conserved)]
+        L.lb_observe.argtypes = [vp, C.POINTER(Window), C.POINTER(Observables)]
         L.lb_time.argtypes = [vp]
         L.lb_time.restype = C.c_long
         L.lb_timing.argtypes = [vp, C.c_int]
@@ -113,7 +131,7 @@ def lib():
         L.lb_batch_last_error.argtypes = [vp]
         L.lb_batch_last_error.restype = C.c_char_p
         for f in ("lb_footprint", "lb_create", "lb_step", "lb_step_batch", "lb_moments", "lb_moments_noalloc",
-                  "lb_timing", "lb_timing_read", "lb_destroy", "lb_batch_footprint", "lb_batch_create",
+                  "lb_observe", "lb_timing", "lb_timing_read", "lb_destroy", "lb_batch_footprint", "lb_batch_create",
                   "lb_batch_step", "lb_batch_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -123,8 +141,9 @@ def lib():
 def make_params(cfg: dict, check_interval: int = 0) -> Params:
     """Convert a parameter dict (paper notation) into ``lb_params``."""
     p = Params()
-    if int(cfg.get("lattice", 19)) != 19:
-        raise ValueError("the GPU library implements D3Q19")
+    lat = int(cfg.get("lattice", 19))
+    if lat not in (9, 19):
+        raise ValueError("lattice must be 9 (D2Q9) or 19 (D3Q19)")
     p.nx, p.ny, p.nz = (int(v) for v in cfg["shape"])
     p.storage = STORAGE[cfg.get("storage", "f32")]
     p.alpha = _d2(*cfg.get("alpha", (1 / 3, 1 / 3)))
@@ -166,6 +185,7 @@ def make_params(cfg: dict, check_interval: int = 0) -> Params:
         p.u_ink = _d3(*noz.get("u_ink", (0.0, 0.0, 0.0)))
         p.lid_rho_y = noz.get("lid_rho_y", 1.0)
     p.check_interval = int(check_interval)
+    p.lattice = lat
     return p
 
 
@@ -264,6 +284,17 @@ class Sim:
             _raise(rc, self._h)
         return cons.as_dict()
 
+    def observe(self, x_lo: int, x_len: int, z_hi: int, y: int = 0) -> dict:
+        """Printing observables (lb_observe) of the section y: the thread in
+        columns x_lo .. x_lo + x_len - 1 below z_hi, and the section's ink
+        pressure and substrate contact."""
+        w = Window(int(x_lo), int(x_len), int(z_hi), int(y))
+        o = Observables()
+        rc = lib().lb_observe(self._h, C.byref(w), C.byref(o))
+        if rc != LB_OK:
+            _raise(rc, self._h)
+        return o.as_dict()
+
     def timing(self, enable: bool = True) -> None:
         """Start (or stop) HIP-event timing of the step kernels."""
         rc = lib().lb_timing(self._h, 1 if enable else 0)
@@ -293,9 +324,12 @@ class Sim:
 
 class Batch:
     """A batch of simulations of one storage form stepped together: each
-    call of step() advances every member by its own step count with one
-    graph launch of the batched kernels over the device slot table (the
-    workspace is a torch uint8 tensor; the stream the batch's own)."""
+    call of step() advances every member (at most MAX_MEMBERS) by its own
+    step count with one graph launch of the batched kernels over the device
+    slot table (the workspace is a torch uint8 tensor; the stream the
+    batch's own)."""
+
+    MAX_MEMBERS = 64  # slots of the device table (lb_batch_step's limit)
 
     def __init__(self, storage: str = "f32", device: str = "cuda:0", stream=None):
         torch = _require_gpu()

@@ -3,13 +3,16 @@
 Requests (a printing set-up, an initial state, a step count) arrive over
 time.  The server keeps every admitted simulation's state resident on the
 GPU and admits waiting requests in arrival order while their device
-footprint (lb_footprint) fits the memory budget.  All admitted simulations
-of one storage form are members of one batch (lb_batch_*): every round is
-ONE lb_batch_step call that advances each member by up to `chunk` steps, a
-replay of the batch's captured graph of batched kernels over the device
-slot table.  Up to `depth` rounds are queued on the batch stream; when a
-round has run, the simulations it finished are read out and released, and
-requests that arrived meanwhile join the next round.
+footprint (lb_footprint) fits the memory budget and a batch has a free
+slot (lb_batch_step takes at most 64 members).  Admitted simulations are
+members of `lanes` batches (lb_batch_*), each on a stream of its own; a new
+member joins the batch with the fewest cells.  Every round is one
+lb_batch_step call per batch that advances each member by up to `chunk`
+steps, a replay of the batch's captured graph of batched kernels over its
+device slot table; the batches' streams run concurrently, so one batch's
+kernels fill the GPU while another's launch drains.  Up to `depth` rounds
+are queued; when a round has run, the simulations it finished are read out
+and released, and requests that arrived meanwhile join the next round.
 
 The comparison point ("sequential") serves the same trace one request at a
 time with plain lb_step calls.
@@ -94,14 +97,17 @@ class Server:
     """Continuous batching over one GPU."""
 
     def __init__(self, budget_bytes: int, chunk: int = 20, device: str = "cuda:0", keep_fields: bool = False,
-                 depth: int = 2):
+                 depth: int = 2, lanes: int = 2):
         if chunk < 1:
             raise ValueError("chunk must be >= 1")
         if depth < 1:
             raise ValueError("depth must be >= 1")
+        if lanes < 1:
+            raise ValueError("lanes must be >= 1")
         self.budget = int(budget_bytes)
         self.chunk = int(chunk)
         self.depth = int(depth)
+        self.lanes = int(lanes)
         self.device = device
         self.keep_fields = keep_fields
 
@@ -116,10 +122,12 @@ class Server:
         forms = {r.cfg.get("storage", "f32") for r in pending}
         if len(forms) != 1:
             raise ValueError(f"one storage form per server run, got {sorted(forms)}")
-        batch = LB.Batch(forms.pop(), device=self.device)
+        form = forms.pop()
+        batches = [LB.Batch(form, device=self.device) for _ in range(self.lanes)]
+        cells = [0] * self.lanes      # cells of each batch's members
         queue = collections.deque()
         active = []                   # admitted members still to be read out
-        rounds = collections.deque()  # (event, members this round finished)
+        rounds = collections.deque()  # (events, members this round finished)
         used = 0
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
@@ -131,32 +139,43 @@ class Server:
             # admission in arrival order, by device footprint (each simulation
             # is created on a stream of its own, so its upload overlaps the
             # queued rounds)
-            while queue:
+            while queue and len(active) < self.lanes * LB.Batch.MAX_MEMBERS:
                 need = LB.footprint(queue[0].cfg)
                 if need > self.budget:
                     raise RuntimeError(f"request {queue[0].id} needs {need} B, above the budget")
                 if used + need > self.budget:
                     break
+                open_lanes = [i for i in range(self.lanes)
+                              if sum(m.lane == i for m in active) < LB.Batch.MAX_MEMBERS]
+                lane = min(open_lanes, key=lambda i: cells[i])
                 req = queue.popleft()
                 sim = LB.Sim(req.cfg, req.ry, req.rb, device=self.device, stream=torch.cuda.Stream(self.device))
-                active.append(_Member(req, sim, need, now()))
+                nx, ny, nz = req.cfg["shape"]
+                active.append(_Member(req, sim, need, now(), lane, nx * ny * nz))
+                cells[lane] += nx * ny * nz
                 used += need
                 stats.peak_bytes = max(stats.peak_bytes, used)
             progressed = False
             # one more round of every member that still has steps to launch
             members = [m for m in active if m.left > 0]
             if members and len(rounds) < self.depth:
-                ks = [min(self.chunk, m.left) for m in members]
-                batch.step([m.sim for m in members], ks)
-                ev = torch.cuda.Event()
-                ev.record(batch.stream)
-                for m, k in zip(members, ks):
-                    m.left -= k
-                rounds.append((ev, [m for m in members if m.left == 0]))
-                stats.launches += 1
+                events = []
+                for i, batch in enumerate(batches):
+                    mine = [m for m in members if m.lane == i]
+                    if not mine:
+                        continue
+                    ks = [min(self.chunk, m.left) for m in mine]
+                    batch.step([m.sim for m in mine], ks)
+                    ev = torch.cuda.Event()
+                    ev.record(batch.stream)
+                    events.append(ev)
+                    for m, k in zip(mine, ks):
+                        m.left -= k
+                    stats.launches += 1
+                rounds.append((events, [m for m in members if m.left == 0]))
                 progressed = True
             # read out and release what the rounds that have run finished
-            while rounds and rounds[0][0].query():
+            while rounds and all(ev.query() for ev in rounds[0][0]):
                 _, finished = rounds.popleft()
                 done = {id(m) for m in finished}
                 for m in finished:
@@ -169,6 +188,7 @@ class Server:
                         log(f"request {m.req.id} done: L={nx} latency {res.latency:.3f} s")
                     m.sim.close()
                     used -= m.need
+                    cells[m.lane] -= m.cells
                 active = [m for m in active if id(m) not in done]
                 progressed = True
             if not progressed:
@@ -178,25 +198,29 @@ class Server:
                     if pending and not queue and pending[0].arrival - now() < 0.002:
                         time.sleep(max(pending[0].arrival - now(), 0.0))
                     else:
-                        rounds[0][0].synchronize()
+                        for ev in rounds[0][0]:
+                            ev.synchronize()
                 elif pending:
                     time.sleep(min(max(pending[0].arrival - now(), 0.0), 0.005))
         torch.cuda.synchronize(self.device)
         stats.wall = now()
-        batch.close()
+        for batch in batches:
+            batch.close()
         return stats
 
 
 class _Member:
     """An admitted request: its simulation, the steps not yet launched, its
-    device bytes and admission time."""
+    device bytes, admission time, batch and cell count."""
 
-    def __init__(self, req, sim, need, admitted):
+    def __init__(self, req, sim, need, admitted, lane, cells):
         self.req = req
         self.sim = sim
         self.left = req.steps
         self.need = need
         self.admitted = admitted
+        self.lane = lane
+        self.cells = cells
 
 
 def run_sequential(requests, device: str = "cuda:0", keep_fields: bool = False, log=None) -> RunStats:

@@ -14,9 +14,10 @@ Parameter dicts use the paper's notation (arXiv:2102.02655):
   u_zlo, u_zhi, rho_zlo, rho_zhi; nozzle = {x0, v, r_in, wall, tip_z, u_ink,
   lid_rho_y} (Sec. II.B).
 
-The paper's own runs are 2-D D2Q9 at density ratio 842 (Sec. III); the
-workloads below are the 3-D D3Q19 printing set-ups at density ratio 1 with a
-power-law ink, as stated for each.
+The paper's own runs are 2-D D2Q9 at density ratio 842 (Sec. III):
+printing_2d() is that set-up in the x-z plane (Table I's Cross inks, the
+density ratio a parameter); the other printing workloads are the 3-D D3Q19
+set-ups at density ratio 1 with a power-law ink, as stated for each.
 """
 from __future__ import annotations
 
@@ -207,3 +208,85 @@ def lattice_units_from_table(nu_mks: float, nu_air_mks: float, tau_air: float, d
     nu_air_lb = CS2 * (tau_air - 0.5)
     dt = dx * dx * nu_air_lb / nu_air_mks
     return dx, dt, nu_mks * dt / (dx * dx)
+
+
+# ------------------------------------------------------------ 2-D (D2Q9)
+
+# Sec. III, Table I, lattice-unit rows: the Cross law's nu0, nu_inf, lambda
+# and exponent for the four alginate inks, and the air's kinematic viscosity
+# of each case (tau_B = 0.54, 0.53, 0.52, 0.52).  The printed LB lambda
+# exponent (10^-5) is garbled; lambda_MKS / dt gives 10^+5, used here.
+TABLE1_LB = {
+    "1%-25C": dict(nu0=0.134, nu_inf=0.0181, lam=3.310e5, m=0.751, tau_b=0.54),
+    "2%-25C": dict(nu0=0.430, nu_inf=0.0045, lam=8.325e5, m=0.713, tau_b=0.53),
+    "3%-25C": dict(nu0=1.991, nu_inf=0.0156, lam=131.0e5, m=0.573, tau_b=0.52),
+    "3%-40C": dict(nu0=0.802, nu_inf=0.0221, lam=21.37e5, m=0.737, tau_b=0.52),
+}
+NU_AIR_MKS = 1.552e-5
+D_MKS = 0.2e-3
+
+
+def ink_speed_lb(case: str, psi: float = 14e-6, rho_ink: float = 1000.0, d_lb: float = 60.0) -> float:
+    """Eq. (fluidconv): v_ink = psi / (rho pi (d/2)^2) (psi = 14 mg/s, a
+    water-like ink density, d = 0.2 mm), in lattice units of the case's
+    dx = d / d_lb and dt = dx^2 nu_air_LB / nu_air_MKS (Eqs. (conv1), (visc))."""
+    v = psi / (rho_ink * np.pi * (D_MKS / 2.0) ** 2)
+    _, dt, _ = lattice_units_from_table(0.0, NU_AIR_MKS, TABLE1_LB[case]["tau_b"], D_MKS, d_lb)
+    return v * dt / (D_MKS / d_lb)
+
+
+def printing_2d(case: str = "1%-25C", v_ratio: float = 1.0, nx: int = 880, nz: int = 240, d: float = 60.0,
+                gap: float = 60.0, wall: float = 4.0, gamma: float = 1.0, head_x0: float = None,
+                u_ink: float = None, storage: str = "f32"):
+    """The paper's 2-D printing set-up (Sec. III, Fig. 1) on D2Q9 in the x-z
+    plane: 880 x 240 nodes, x periodic, a no-slip substrate at z = 0, the top
+    face at the air density outside the nozzle and the inlet lid over its
+    bore; a nozzle channel of width d (walls `wall` nodes thick) from z = gap
+    through the top, starting full of ink at 3/4 of the box (the right side)
+    and moving towards -x at v_ratio * v_ink; the ink enters at v_ink
+    (Eq. (fluidconv), or u_ink) in the head frame.  Ink: Table I's Cross law
+    for `case`; density ratio gamma = rho_Y^0 / rho_B^0 = (1 - alpha_B) /
+    (1 - alpha_Y) with alpha_B = 4/9 (phi_i^B = w_i); tau in [0.51, 2.0]."""
+    c = TABLE1_LB[case]
+    v = ink_speed_lb(case) if u_ink is None else float(u_ink)
+    alpha_b = 4.0 / 9.0
+    alpha_y = 1.0 - (1.0 - alpha_b) / gamma
+    x0 = 0.75 * nx if head_x0 is None else float(head_x0)
+    return base_params(
+        (nx, 1, nz),
+        lattice=9,
+        alpha=(alpha_y, alpha_b),
+        rho0=(float(gamma), 1.0),
+        tau_b=c["tau_b"],
+        rheology="cross",
+        nu0=c["nu0"],
+        nu_inf=c["nu_inf"],
+        m=c["m"],
+        tau_min=0.51,
+        tau_max=2.0,
+        face_zlo="wall",
+        face_zhi="pressure",
+        rho_zhi=(0.0, 1.0),
+        nozzle=dict(x0=(x0, 0.0), v=(-v_ratio * v, 0.0), r_in=d / 2.0, wall=float(wall), tip_z=float(gap),
+                    u_ink=(0.0, 0.0, -v), lid_rho_y=float(gamma)),
+        storage=storage,
+        **{"lambda": c["lam"]},
+    )
+
+
+def droplet_2d(n: int = 48, radius: float = 12.0, seed: int = 2102, trace: float = 0.02, noise: float = 1e-3,
+               storage: str = "f64", tau: float = 1.0):
+    """Static 2-D droplet on D2Q9: a periodic n x 1 x n box, a disc of ink
+    (rho_Y = 1, air trace) centred at ((n-1)/2, (n-1)/2) in air, Newtonian tau
+    for both colours, independent U(-noise, noise) added to rho_Y then rho_B
+    in C order from default_rng(seed); alpha = 4/9 (phi_i = w_i)."""
+    cfg = base_params((n, 1, n), lattice=9, alpha=(4.0 / 9.0, 4.0 / 9.0), tau_b=tau, tau_y=tau, storage=storage)
+    z, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    c = (n - 1) / 2.0
+    inside = ((x - c) ** 2 + (z - c) ** 2 <= radius ** 2)[:, None, :]
+    ry = np.where(inside, 1.0, trace)
+    rb = np.where(inside, trace, 1.0)
+    rng = np.random.default_rng(seed)
+    ry = ry + rng.uniform(-noise, noise, size=ry.shape)
+    rb = rb + rng.uniform(-noise, noise, size=rb.shape)
+    return cfg, ry, rb

@@ -146,3 +146,26 @@ def test_batch_arguments_rejected_without_the_gpu(lib):
     assert out.value is None
     assert lib.lb_batch_step(None, None, None, 0) == LB.LB_EINVAL
     assert lib.lb_batch_destroy(None) == LB.LB_EINVAL
+
+
+def test_d2q9_validation_and_footprint(lib):
+    """D2Q9 handles live in the x-z plane (ny = 1) with FP64 or FP32
+    storage; their population sets are 2 x 9 planes."""
+    cfg = W.base_params((64, 1, 32), lattice=9, alpha=(4 / 9, 4 / 9), storage="f32")
+    b32 = LB.footprint(cfg)
+    N = 64 * 32
+    assert 2 * 18 * N * 4 < b32 < LB.footprint(dict(cfg, lattice=19))
+    for change, msg in [(dict(shape=(64, 2, 32)), "ny must be 1"),
+                        (dict(storage="bf16dev"), "LB_F64 or LB_F32"),
+                        (dict(body_g=(0.0, 1e-6, 0.0)), "y components"),
+                        (dict(lattice=15), "lattice must be")]:
+        bad = dict(cfg, **change)
+        if change.get("lattice") == 15:
+            p = LB.make_params(dict(cfg))
+            p.lattice = 15
+            n = C.c_size_t()
+            assert lib.lb_footprint(C.byref(p), C.byref(n)) == LB.LB_EINVAL
+            continue
+        with pytest.raises(LB.LBError) as e:
+            LB.footprint(bad)
+        assert e.value.status == LB.LB_EINVAL and msg in str(e.value)

@@ -63,7 +63,7 @@ def closure(c, c0):
     return c["mass"] - c0["mass"] - (c["mass_wall"] + c["mass_open"] + c["mass_created"] - c["mass_deleted"])
 
 
-def parity(G, O, cfg, ry, rb, steps, label, u=None, storages=("f64", "f32"), ledger=True, fp32_from=0):
+def parity(G, O, cfg, ry, rb, steps, label, u=None, storages=("f64", "f32"), ledger=True, fp32_from=0, tol=None):
     """Run the oracle and the GPU from the same inputs; compare the fields at
     each step count in `steps` (FP32 from step `fp32_from` on) and, with
     `ledger`, the FP64 mass ledger; on both sides the ledger closes."""
@@ -83,7 +83,8 @@ def parity(G, O, cfg, ry, rb, steps, label, u=None, storages=("f64", "f32"), led
             e = (rel(g[0], o[0]), rel(g[1], o[1]), rel(g[2], o[2]))
             say(f"{label} {st} t={t}: rel-L2 rho_Y {e[0]:.3e} rho_B {e[1]:.3e} u {e[2]:.3e}")
             if st == "f64" or t >= fp32_from:
-                assert max(e) <= TOL[st], (label, st, t, e)
+                bound = (tol or {}).get(st, (TOL[st],) * 3)
+                assert all(a <= b for a, b in zip(e, bound)), (label, st, t, e, bound)
             if ledger:
                 gc, oc = g[3], o[3]
                 for key in ("mass", "mass_wall", "mass_open", "mass_created", "mass_deleted"):
@@ -174,6 +175,28 @@ def test_power_law_slit_on_both_clamps(G, O, n):
     u = np.zeros((H, ny, nx, 3))
     u[..., 0] = prof[:, None, None]
     parity(G, O, cfg, ry, rb, (1, 100, 400), f"slit n={n}", u=u, ledger=False)
+
+
+@pytest.mark.parametrize("lattice", [19, 9])
+def test_cross_law_slit_spans_the_solve(G, O, lattice):
+    """Table I's 1% Cross ink in a body-force slit started from rest: the
+    strain rate runs from zero at the centre to its largest at the walls, so
+    the relaxation-time solve is exercised across its range, including the
+    band (s ~ 1e-6) where a converged iterate once fell out of the bracket.
+    FP32 bound on u 5e-4, ten times the 5.0e-5 measured at step 100 (D3Q19;
+    1.3e-5 on D2Q9): the ink's non-equilibrium stress is a difference of
+    second moments of size rho c_s^2 ~ 0.33 that cancel to ~1e-6 here, so
+    FP32 resolves it to a few per cent, and in the Cross law's thinning band
+    (lambda gdot ~ 1) the relaxation time follows it."""
+    H, g = 24, 1e-6
+    ny = 4 if lattice == 19 else 1
+    cfg = W.base_params((8, ny, H), lattice=lattice, alpha=((1 / 3, 1 / 3) if lattice == 19 else (4 / 9, 4 / 9)),
+                        tau_b=0.54, rheology="cross", nu0=0.134, nu_inf=0.0181, m=0.751, tau_min=0.51, tau_max=2.0,
+                        face_zlo="wall", face_zhi="wall", body_g=(g, 0, 0))
+    cfg["lambda"] = 3.31e5
+    ry, rb = np.ones((H, ny, 8)), np.zeros((H, ny, 8))
+    parity(G, O, cfg, ry, rb, (1, 100, 400), f"cross slit D{'3Q19' if lattice == 19 else '2Q9'}", ledger=False,
+           fp32_from=100, tol={"f32": (1e-5, 1e-5, 5e-4)})
 
 
 # ----------------------------------------------------------- density ratio
