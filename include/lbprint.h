@@ -126,7 +126,13 @@ typedef struct lb_handle lb_handle;
 /* Bytes of device workspace a handle needs for these parameters (pure host
  * computation; used for admission).  Includes the padding between population
  * planes (256 B, or 1 MiB + 256 B for planes of 16 MiB and more) and the
- * full-box auxiliary arrays.  LB_EINVAL on bad parameters. */
+ * boundary-only arrays (moment sets, colour fields and macro fields of the
+ * cells next to the z faces and the head), which a D3Q19 box with z walls
+ * keeps for three layers at each face and a window of columns around the
+ * head (the smallest divisor of nx, resp. ny, of at least 2 ceil(r_out) + 16;
+ * head speed at most 1/2 per step), and
+ * a periodic box, a faster head or a D2Q9 box for every cell.  LB_EINVAL on
+ * bad parameters. */
 lb_status lb_footprint(const lb_params *p, size_t *bytes);
 
 /* Create a simulation.  rho_y, rho_b: host FP64 [z][y][x] initial densities;

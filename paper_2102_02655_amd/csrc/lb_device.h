@@ -74,6 +74,15 @@ struct DevParams {
     double x0noz[2];           // head axis (x, y) at t = 0
     double u_in[3];            // u_ink + v_nozzle, Eq. (movnozzle)
     double lid_rho;
+    // Boundary-only arrays (moment sets and colour fields of the prepared
+    // cells, macro fields for the next step's boundary rules): component
+    // stride NA.  aux = 0: one slot per cell of the box (NA = N).  aux = 1:
+    // compact slots (aidx) for the az_lo / az_hi layers at the z faces and
+    // the head region -- planes ah_z0 .. nz - az_hi - 1, columns taken
+    // modulo (aw, ah) from a_head0 on; slot NA - 1 is a sink for cells
+    // outside both (never used by a correct step).
+    int aux, az_lo, az_hi, ah_z0, aw, ah;
+    long long NA, a_head0;
 };
 
 // Head axis of the previous and the current step, wrapped into the box.
@@ -82,6 +91,24 @@ struct HeadPos {
 };
 
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// Slot of cell (x, y, z) (inside the box) in the boundary-only arrays.  The
+// head region's window (aw x ah columns) is wider than every set of cells a
+// step or two consecutive steps touch around the head axis (the head box,
+// its neighbours, the macro fields written for the next step), so no two
+// cells in use at once share a slot.
+__host__ __device__ inline long long aidx(const DevParams &P, int x, int y, int z)
+{
+    const long long pl = (long long)P.nx * P.ny;
+    if (!P.aux) return (long long)z * pl + (long long)y * P.nx + x;
+    if (z < P.az_lo) return (long long)z * pl + (long long)y * P.nx + x;
+    if (z >= P.nz - P.az_hi) return (long long)(P.az_lo + z - (P.nz - P.az_hi)) * pl + (long long)y * P.nx + x;
+    if (z < P.ah_z0 || !P.has_nozzle) return P.NA - 1;
+    // power-of-two windows (the usual case) by mask
+    const int xm = (P.aw & (P.aw - 1)) == 0 ? (x & (P.aw - 1)) : x % P.aw;
+    const int ym = (P.ah & (P.ah - 1)) == 0 ? (y & (P.ah - 1)) : y % P.ah;
+    return P.a_head0 + ((long long)(z - P.ah_z0) * P.ah + ym) * P.aw + xm;
+}
 
 // ---------------------------------------------------------------- geometry
 // Decided in FP64 with every operation rounded as written (no FMA
@@ -364,22 +391,22 @@ struct PopSrc<R, ST_PLAIN> {
 // pressure faces).  st: the class of x - c_i.
 template <typename R, int I, bool FULL = true>
 __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, const R *__restrict__ mac, int x,
-                                          int y, int z, long long cell, bool near, const int (&cc)[3][3], int st,
+                                          int y, int z, long long acell, bool near, const int (&cc)[3][3], int st,
                                           R Tout, R Yout, Mom<R> &M, Flux &fl)
 {
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-    const long long N = P.N;
+    const long long N = P.NA;  // mac: boundary-only arrays, cell = this cell's slot
     const R wi = R(lbq::w(I));
     R T, Yv;
     if (st == ST_OPEN_LO || st == ST_OPEN_HI) {
         const bool lo = st == ST_OPEN_LO;
         const double rw0 = lo ? P.rho_lo[0] : P.rho_hi[0], rw1 = lo ? P.rho_lo[1] : P.rho_hi[1];
         // u_w = (3 u(x) - u(x + c_i)) / 2 at t-1 when x + c_i was fluid
-        R ux = mac[2 * N + cell], uy = mac[3 * N + cell], uz = mac[4 * N + cell];
+        R ux = mac[2 * N + acell], uy = mac[3 * N + acell], uz = mac[4 * N + acell];
         int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
         int s1 = classify_cc(P, cc[1 + X][1 + Yc], z1, near);
         if (s1 == ST_FLUID) {
-            long long c1 = ((long long)z1 * P.ny + y1) * P.nx + x1;
+            const long long c1 = aidx(P, x1, y1, z1);
             ux = (R(3) * ux - mac[2 * N + c1]) * R(0.5);
             uy = (R(3) * uy - mac[3 * N + c1]) * R(0.5);
             uz = (R(3) * uz - mac[4 * N + c1]) * R(0.5);
@@ -416,16 +443,16 @@ __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, 
             if (U0 * X + U1 * Yc + U2 * Z != 0.0) {
                 // rho_w by quadratic extrapolation to the link midpoint from
                 // x, x + c_i, x + 2 c_i (the inward direction), at t-1
-                R r0Y = mac[0 * N + cell], r0B = mac[1 * N + cell];
+                R r0Y = mac[0 * N + acell], r0B = mac[1 * N + acell];
                 int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
                 int s1 = classify_cc(P, cc[1 + X][1 + Yc], z1, near);
                 if (s1 == ST_FLUID) {
-                    long long c1 = ((long long)z1 * P.ny + y1) * P.nx + x1;
+                    const long long c1 = aidx(P, x1, y1, z1);
                     R r1Y = mac[0 * N + c1], r1B = mac[1 * N + c1];
                     int x2 = X ? wrap(x1 + X, P.nx) : x1, y2 = Yc ? wrap(y1 + Yc, P.ny) : y1, z2 = z1 + Z;
                     int s2 = classify(P, H.hx_p, H.hy_p, x2, y2, z2, near);
                     if (s2 == ST_FLUID) {
-                        long long c2 = ((long long)z2 * P.ny + y2) * P.nx + x2;
+                        const long long c2 = aidx(P, x2, y2, z2);
                         R r2Y = mac[0 * N + c2], r2B = mac[1 * N + c2];
                         rwY = (R(15) * r0Y - R(10) * r1Y + R(3) * r2Y) * R(0.125);
                         rwB = (R(15) * r0B - R(10) * r1B + R(3) * r2B) * R(0.125);
@@ -471,6 +498,7 @@ __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, c
     int st[lbq::Q];
     int cc[3][3];
     column_classes(P, H, x, y, near && !first, cc);
+    const long long acell = aidx(P, x, y, z);  // slot in the macro fields
     [&]<int... I>(std::integer_sequence<int, I...>) {
         (
             [&] {
@@ -500,7 +528,7 @@ __device__ __forceinline__ void pull_all(const DevParams &P, const HeadPos &H, c
                     mom_add<R, I, FULL>(M, T, Y);
                 } else {
                     src.template finish<lbq::opp(I)>(P, raw[I], T, Y);
-                    pull_rule<R, I, FULL>(P, H, mac, x, y, z, cell, near, cc, st[I], T, Y, M, fl);
+                    pull_rule<R, I, FULL>(P, H, mac, x, y, z, acell, near, cc, st[I], T, Y, M, fl);
                 }
             }(),
             ...);

@@ -188,7 +188,6 @@ __device__ __forceinline__ void fused_body(const DevParams &P, StepGeom *__restr
     const int x0 = tx * 64, y0 = ty * TY, z0 = tz * FG.zlen;
     const int z1 = min(z0 + FG.zlen, P.nz);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long N = P.N;
 
     int cx, cy, row, col;
     bool active = true;
@@ -298,11 +297,12 @@ __device__ __forceinline__ void fused_body(const DevParams &P, StepGeom *__restr
             collide_state<R>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,
                              (unsigned)(ccell * (long long)sizeof(R)), rY, rB, u);
             if (macro_needed(P, H, xw, yw, c)) {
-                mac_next[ccell] = rY;
-                mac_next[N + ccell] = rB;
-                mac_next[2 * N + ccell] = u[0];
-                mac_next[3 * N + ccell] = u[1];
-                mac_next[4 * N + ccell] = u[2];
+                const long long a = aidx(P, xw, yw, c), NA = P.NA;
+                mac_next[a] = rY;
+                mac_next[NA + a] = rB;
+                mac_next[2 * NA + a] = u[0];
+                mac_next[3 * NA + a] = u[1];
+                mac_next[4 * NA + a] = u[2];
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -325,15 +325,16 @@ __device__ __forceinline__ void fused_body(const DevParams &P, StepGeom *__restr
                 if (prep) {
                     // boundary cell (pulled with the boundary rules), head
                     // solid (wall densities) or node just created
-                    cN = chi[cell];
-                    cY = chi[N + cell];
-                    cB = chi[2 * N + cell];
+                    const long long a = aidx(P, xw, yw, zp), NA = P.NA;
+                    cN = chi[a];
+                    cY = chi[NA + a];
+                    cB = chi[2 * NA + a];
                     fluid = !(shell_c && (double)zp >= P.tip_z);
                     if (own && fluid) {
-                        M.dm[0] = momd[cell];
-                        M.dm[1] = momd[N + cell];
+                        M.dm[0] = momd[a];
+                        M.dm[1] = momd[NA + a];
 #pragma unroll
-                        for (int m = 2; m < NMOM; ++m) M.m[m] = mom[(m - 2) * N + cell];
+                        for (int m = 2; m < NMOM; ++m) M.m[m] = mom[(m - 2) * NA + a];
                     }
                 } else {
                     if (own)
@@ -423,7 +424,6 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
     const int x0 = tx * 64, y0 = ty * TY, z0 = tz * FG.zlen;
     const int z1 = min(z0 + FG.zlen, P.nz);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long long N = P.N;
     const long long plane_sz = (long long)P.nx * P.ny;
     const unsigned long long pstride = (unsigned long long)P.NP * sizeof(E);
 
@@ -484,11 +484,12 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
                 collide_state<R, ST>(P, C, G, c, reinterpret_cast<char *>(dst), pstride,
                                      (unsigned)(ccell * (long long)sizeof(E)), rY, rB, u, mo_dst, ccell);
                 if (macro_needed(P, H, xw, yw, c)) {
-                    mac_next[ccell] = rY;
-                    mac_next[N + ccell] = rB;
-                    mac_next[2 * N + ccell] = u[0];
-                    mac_next[3 * N + ccell] = u[1];
-                    mac_next[4 * N + ccell] = u[2];
+                    const long long a = aidx(P, xw, yw, c), NA = P.NA;
+                    mac_next[a] = rY;
+                    mac_next[NA + a] = rB;
+                    mac_next[2 * NA + a] = u[0];
+                    mac_next[3 * NA + a] = u[1];
+                    mac_next[4 * NA + a] = u[2];
                 }
             }
             }
@@ -644,15 +645,16 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
             mom_zero(M);
             bool fluid = true;
             if (J.prep) {
-                cN = chi[J.cell];
-                cY = chi[N + J.cell];
-                cB = chi[2 * N + J.cell];
+                const long long a = aidx(P, xw, yw, J.zp), NA = P.NA;
+                cN = chi[a];
+                cY = chi[NA + a];
+                cB = chi[2 * NA + a];
                 fluid = !(shell_c && (double)J.zp >= P.tip_z);
                 if (J.own && fluid) {
-                    M.dm[0] = momd[J.cell];
-                    M.dm[1] = momd[N + J.cell];
+                    M.dm[0] = momd[a];
+                    M.dm[1] = momd[NA + a];
 #pragma unroll
-                    for (int m = 2; m < NMOM; ++m) M.m[m] = mom[(m - 2) * N + J.cell];
+                    for (int m = 2; m < NMOM; ++m) M.m[m] = mom[(m - 2) * NA + a];
                 }
             } else {
                 // one code path for tile and ring cells (a branch here lets

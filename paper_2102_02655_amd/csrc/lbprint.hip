@@ -88,21 +88,23 @@ __device__ __forceinline__ void cell_xyz(const DevParams &P, long long cell, int
     x = (int)(r - (long long)y * P.nx);
 }
 
+// colour fields at slot `cell` of arrays with component stride `st`
 template <typename R>
-__device__ __forceinline__ void write_chi(const DevParams &P, R *chi, long long cell, double rY, double rB)
+__device__ __forceinline__ void write_chi(const DevParams &P, R *chi, long long cell, long long st, double rY,
+                                          double rB)
 {
     double cN, cY, cB;
     chi_of<double>(P, rY, rB, cN, cY, cB);
     chi[cell] = R(cN);
-    chi[P.N + cell] = R(cY);
-    chi[2 * P.N + cell] = R(cB);
+    chi[st + cell] = R(cY);
+    chi[2 * st + cell] = R(cB);
 }
 
-// densities of a fluid cell from its FP64 masses
-__device__ __forceinline__ void dens(const DevParams &P, const double *__restrict__ momd, long long c, double &rY,
-                                    double &rB)
+// densities of a fluid cell from its FP64 masses (slot c, component stride st)
+__device__ __forceinline__ void dens(const DevParams &P, const double *__restrict__ momd, long long c, long long st,
+                                    double &rY, double &rB)
 {
-    rY = momd[P.N + c];
+    rY = momd[st + c];
     rB = P.rho_ref + momd[c] - rY;
 }
 
@@ -154,7 +156,10 @@ __global__ __launch_bounds__(TPB) void k_init(DevParams P, const StepGeom *__res
 // Pull + moments of one cell at step t: moment set, colour fields, and into
 // acc the boundary fluxes of its pull (when fluxes) and, for a node the head
 // covers at t, its deleted mass.
-template <typename R, typename PS>
+// RO (read-out): masses and momentum into full-box arrays at the cell's
+// index; else (boundary preparation) the whole moment set and the colour
+// fields into the boundary-only arrays at the cell's slot.
+template <typename R, bool RO, typename PS>
 __device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &H, const PS &src,
                                              const R *__restrict__ mac, double *__restrict__ momd,
                                              R *__restrict__ mom, R *__restrict__ chi, long long cell, int x, int y,
@@ -169,11 +174,19 @@ __device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &
     Flux fl = {0.0, 0.0, 0.0, 0.0};
     pull_all<R, true>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
     if (!sc) {
-        momd[cell] = M.dm[0];
-        momd[P.N + cell] = M.dm[1];
+        if constexpr (RO) {
+            momd[cell] = M.dm[0];
+            momd[P.N + cell] = M.dm[1];
 #pragma unroll
-        for (int q = 2; q < NMOM; ++q) mom[(q - 2) * P.N + cell] = M.m[q];
-        write_chi<R>(P, chi, cell, M.dm[1], P.rho_ref + M.dm[0] - M.dm[1]);
+            for (int q = 2; q < 5; ++q) mom[(q - 2) * P.N + cell] = M.m[q];
+        } else {
+            const long long a = aidx(P, x, y, z), NA = P.NA;
+            momd[a] = M.dm[0];
+            momd[NA + a] = M.dm[1];
+#pragma unroll
+            for (int q = 2; q < NMOM; ++q) mom[(q - 2) * NA + a] = M.m[q];
+            write_chi<R>(P, chi, a, NA, M.dm[1], P.rho_ref + M.dm[0] - M.dm[1]);
+        }
     } else {
         acc[4] += M.dm[1];
         acc[5] += P.rho_ref + M.dm[0] - M.dm[1];
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(TPB) void k_moments(DevParams P, const StepGeom *__
          cell += (long long)gridDim.x * TPB) {
         int x, y, z;
         cell_xyz(P, cell, x, y, z);
-        moments_cell<R>(P, H, src, mac, momd, mom, chi, cell, x, y, z, first != 0, true, acc, any);
+        moments_cell<R, true>(P, H, src, mac, momd, mom, chi, cell, x, y, z, first != 0, true, acc, any);
     }
     block_sum<NSLOT>(acc, slots + (long long)blockIdx.x * NSLOT, false);
 }
@@ -242,7 +255,8 @@ __device__ __forceinline__ void pre_body(const DevParams &P, StepGeom *__restric
             int x = ((B.x0 + ix) % P.nx + P.nx) % P.nx, y = ((B.y0 + iy) % P.ny + P.ny) % P.ny, z = B.z0 + iz;
             if (z < 0 || z >= P.nz) continue;
             if (bi > 0 && in_box(P, b0, x, y, z)) continue;
-            moments_cell<R>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc, any);
+            moments_cell<R, false>(P, H, src, mac, momd, mom, chi, cidx(P, x, y, z), x, y, z, first != 0, true, acc,
+                                   any);
         }
     }
     if (!__syncthreads_or(any)) return;
@@ -269,6 +283,10 @@ __device__ __forceinline__ void create_body(const DevParams &P, const StepGeom *
 {
     const HeadPos H = G->H;
     const int bx0 = G->hb.x0, by0 = G->hb.y0, bz0 = G->hb.z0, bw = G->hb.w, bh = G->hb.h, bd = G->hb.d;
+    // the read-out (commit = 0) keeps full-box arrays of masses and momentum;
+    // the step the boundary-only arrays
+    const bool ro = commit == 0;
+    const long long st = ro ? P.N : P.NA;
     double acc[2] = {0.0, 0.0};
     const long long total = (long long)bw * bh * bd;
     for (long long k = (long long)bid * TPB + threadIdx.x; k < total; k += (long long)nblk * TPB) {
@@ -287,11 +305,11 @@ __device__ __forceinline__ void create_body(const DevParams &P, const StepGeom *
             const bool in = zz >= 0 && zz < P.nz;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
             use[i] = in && !is_solid(P, H.hx_p, H.hy_p, xx, yy, zz) && !is_solid(P, H.hx_c, H.hy_c, xx, yy, zz);
-            nc[i] = use[i] ? cidx(P, xx, yy, zz) : cidx(P, x, y, z);
+            nc[i] = use[i] ? (ro ? cidx(P, xx, yy, zz) : aidx(P, xx, yy, zz)) : (ro ? cidx(P, x, y, z) : aidx(P, x, y, z));
         }
         double nd[lbq::Q][2];
 #pragma unroll
-        for (int i = 1; i < lbq::Q; ++i) dens(P, momd, nc[i], nd[i][0], nd[i][1]);
+        for (int i = 1; i < lbq::Q; ++i) dens(P, momd, nc[i], st, nd[i][0], nd[i][1]);
         double sY = 0.0, sB = 0.0;
         int cnt = 0;
 #pragma unroll
@@ -301,7 +319,7 @@ __device__ __forceinline__ void create_body(const DevParams &P, const StepGeom *
             cnt += use[i] ? 1 : 0;
         }
         double rY = cnt ? sY / cnt : 0.0, rB = cnt ? sB / cnt : P.rho0[1];
-        long long cell = cidx(P, x, y, z);
+        const long long cell = ro ? cidx(P, x, y, z) : aidx(P, x, y, z);
         // moments of f^eq(rho_bar, v): drho, rho_Y, j = rho v, second moments
         double vx = P.vnoz[0], vy = P.vnoz[1];
         double rho = rY + rB;
@@ -312,9 +330,9 @@ __device__ __forceinline__ void create_body(const DevParams &P, const StepGeom *
                           iso + rho * vx * vx, iso + rho * vy * vy, iso, rho * vx * vy, 0.0, 0.0,
                           rY * (cY2 + vx * vx), rY * (cY2 + vy * vy), rY * cY2, rY * vx * vy, 0.0, 0.0};
         momd[cell] = m[0];
-        momd[P.N + cell] = m[1];
-        for (int q = 2; q < NMOM; ++q) mom[(q - 2) * P.N + cell] = R(m[q]);
-        write_chi<R>(P, chi, cell, rY, rB);
+        momd[st + cell] = m[1];
+        for (int q = 2; q < (ro ? 5 : NMOM); ++q) mom[(q - 2) * st + cell] = R(m[q]);
+        if (!ro) write_chi<R>(P, chi, cell, st, rY, rB);
         acc[0] += rY;
         acc[1] += rB;
     }
@@ -354,11 +372,11 @@ __device__ __forceinline__ void wall_body(const DevParams &P, const StepGeom *__
             const bool in = zz >= 0 && zz < P.nz;
             int xx = wrap(x + lbq::cx(i), P.nx), yy = wrap(y + lbq::cy(i), P.ny);
             use[i] = in && !is_solid(P, H.hx_c, H.hy_c, xx, yy, zz);
-            nc[i] = use[i] ? cidx(P, xx, yy, zz) : cidx(P, x, y, z);
+            nc[i] = use[i] ? aidx(P, xx, yy, zz) : aidx(P, x, y, z);
         }
         double nd[lbq::Q][2];
 #pragma unroll
-        for (int i = 1; i < lbq::Q; ++i) dens(P, momd, nc[i], nd[i][0], nd[i][1]);
+        for (int i = 1; i < lbq::Q; ++i) dens(P, momd, nc[i], P.NA, nd[i][0], nd[i][1]);
         double nY = 0.0, nB = 0.0, den = 0.0;
 #pragma unroll
         for (int i = 1; i < lbq::Q; ++i) {
@@ -367,10 +385,10 @@ __device__ __forceinline__ void wall_body(const DevParams &P, const StepGeom *__
             nB += use[i] ? wi * nd[i][1] : 0.0;
             den += use[i] ? wi : 0.0;
         }
-        long long cell = cidx(P, x, y, z);
+        const long long cell = aidx(P, x, y, z);
         double sY = den > 0.0 ? P.zeta_noz[0] * nY / den : 0.0;
         double sB = den > 0.0 ? P.zeta_noz[1] * nB / den : 0.0;
-        write_chi<R>(P, chi, cell, sY, sB);
+        write_chi<R>(P, chi, cell, P.NA, sY, sB);
     }
 }
 
@@ -429,7 +447,7 @@ __device__ __forceinline__ void ghost_body(const DevParams &P, const StepGeom *_
             if (is_solid(P, H.hx_c, H.hy_c, xx, yy, zin)) continue;
             double wi = lbq::w(i);
             double nrY, nrB;
-            dens(P, momd, cidx(P, xx, yy, zin), nrY, nrB);
+            dens(P, momd, aidx(P, xx, yy, zin), P.NA, nrY, nrB);
             nY += wi * nrY;
             nB += wi * nrB;
             den += wi;
@@ -469,7 +487,7 @@ __global__ __launch_bounds__(TPB) void k_output(DevParams P, const StepGeom *__r
         bool solid = !far_from_head(P, H.hx_c, H.hy_c, x, y) && is_solid(P, H.hx_c, H.hy_c, x, y, z);
         double rY = 0.0, rB = 0.0, U[3] = {0.0, 0.0, 0.0};
         if (!solid) {
-            dens(P, momd, cell, rY, rB);
+            dens(P, momd, cell, P.N, rY, rB);
             double r = rY + rB;
             double j[3] = {(double)mom[cell], (double)mom[P.N + cell], (double)mom[2 * P.N + cell]};
             double F[3];
@@ -552,7 +570,7 @@ __global__ __launch_bounds__(TPB) void k_observe(DevParams P, const StepGeom *__
         const int z = (int)(k / P.nx), x = (int)(k - (long long)z * P.nx);
         if (is_solid(P, H.hx_c, H.hy_c, x, ysec, z)) continue;
         double rY, rB;
-        dens(P, momd, cidx(P, x, ysec, z), rY, rB);
+        dens(P, momd, cidx(P, x, ysec, z), P.N, rY, rB);
         if (!(rY * P.rho0[1] > rB * P.rho0[0])) continue;  // rho^N > 0
         v[4] = fmax(v[4], rY * cY2 + rB * cB2 - p0);
         v[5] += z == 0 ? 1.0 : 0.0;
@@ -654,6 +672,8 @@ size_t al(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
 
 struct Layout {
     size_t pops, dmo, momd, mom, chi, ghost, mac, pend, part, cumpre, cumc, pendc, red, geo, tab, total;
+    long long NA;    // slots of the boundary-only arrays (momd, mom, chi, mac)
+    size_t ro;       // read-out arrays (masses, momentum) inside the spare population buffer
     long long nbm;   // blocks of the whole-box read-out kernels
     FusedGrid fg;    // tiling of the fused step kernel
     long long nbf;   // its block count
@@ -874,6 +894,66 @@ FusedGrid fused_grid(const lb_params &p, int ty, long long want_blocks = 512)
     return g;
 }
 
+// Boundary-only arrays (moment sets and colour fields of the prepared cells,
+// macro fields for the next step's boundary rules).  Only the cells next to
+// the z faces and around the head use them, so a D3Q19 box with walls keeps
+// them compact (DevParams::aux): three layers at each z face (the prepared
+// face planes and the two planes whose macro fields the face rules
+// extrapolate from), and the head region from four planes below the tip up,
+// its columns taken modulo a window.  A step touches the head box (r_out + 2
+// around the axis at the step's two positions, rounded out), one more cell
+// for neighbour reads, two for the extrapolation, and the macro fields
+// within r_out + 4 of the axis for the next step, which reads them around
+// the next position: at most 2 ceil(r_out) + 12 consecutive columns over two
+// steps of a head moving at most half a cell per step.  The window is the
+// smallest divisor of the box's extent that is at least 2 ceil(r_out) + 16
+// (the extent itself if there is none), so that columns sharing a slot are
+// a whole number of windows apart also across the periodic boundary.
+// Periodic boxes, faster heads and boxes the compact form would not shrink
+// keep one slot per cell.
+int window_of(int extent, int need)
+{
+    for (int d = need; d < extent; ++d)
+        if (extent % d == 0) return d;
+    return extent;
+}
+
+struct AuxPlan {
+    int aux, az_lo, az_hi, ah_z0, aw, ah;
+    long long NA, a_head0;
+};
+
+AuxPlan aux_plan(const lb_params &p)
+{
+    AuxPlan a;
+    std::memset(&a, 0, sizeof(a));
+    const long long N = (long long)p.nx * p.ny * p.nz, pl = (long long)p.nx * p.ny;
+    a.NA = N;
+    const int az = 3;
+    if (is_d2(p) || p.face_zlo == LB_FACE_PERIODIC || p.nz <= 2 * az + 1) return a;
+    long long head = 0;
+    int z0 = p.nz - az, aw = 0, ah = 0;
+    if (p.has_nozzle) {
+        if (std::fabs(p.noz_v[0]) > 0.5 || std::fabs(p.noz_v[1]) > 0.5) return a;
+        const int win = 2 * (int)std::ceil(p.noz_r_in + p.noz_wall) + 16;
+        aw = window_of(p.nx, win);
+        ah = window_of(p.ny, win);
+        z0 = std::max(az, (int)std::floor(p.noz_tip_z) - 4);
+        z0 = std::min(z0, p.nz - az);
+        head = (long long)(p.nz - az - z0) * aw * ah;
+    }
+    const long long NA = 2LL * az * pl + head + 1;  // + the sink slot
+    if (NA >= N) return a;
+    a.aux = 1;
+    a.az_lo = a.az_hi = az;
+    a.ah_z0 = z0;
+    a.aw = aw;
+    a.ah = ah;
+    a.NA = NA;
+    a.a_head0 = 2LL * az * pl;
+    return a;
+}
+
 Layout layout_of(const lb_params &p)
 {
     Layout L;
@@ -909,16 +989,22 @@ Layout layout_of(const lb_params &p)
     off += 2 * al(pop_set_bytes(N, p.storage, lattice_q(p)));
     L.dmo = off;  // source moments of the reduced storage forms (two copies)
     if (reduced(p.storage)) off += 2 * al(NMO * (size_t)plane_stride(N, LB_F32) * 4);
+    const long long NA = aux_plan(p).NA;
+    L.NA = NA;
     L.momd = off;
-    off += al(2 * (size_t)N * 8);
+    off += al(2 * (size_t)NA * 8);
     L.mom = off;
-    off += al(NMOMR * (size_t)N * rs);
+    off += al(NMOMR * (size_t)NA * rs);
     L.chi = off;
-    off += al(NCHI * (size_t)N * rs);
+    off += al(NCHI * (size_t)NA * rs);
     L.ghost = off;
     off += al(2 * NCHI * (size_t)p.nx * p.ny * rs);
     L.mac = off;
-    off += 2 * al(NMAC * (size_t)N * rs);
+    off += 2 * al(NMAC * (size_t)NA * rs);
+    // the read-out's masses (FP64) and momentum, after the largest staged
+    // output (five FP64 fields) in the spare population buffer; D2Q9's
+    // read-out writes the boundary-only arrays, which are full-box there
+    L.ro = al(5 * (size_t)N * 8);
     L.pend = off;
     off += al((size_t)L.nbm * NSLOT * 8);
     L.part = off;
@@ -1062,6 +1148,15 @@ DevParams make_dev(const lb_params &p)
         P.u_in[2] = p.u_ink[2];
         P.lid_rho = p.lid_rho_y;
     }
+    const AuxPlan a = aux_plan(p);
+    P.aux = a.aux;
+    P.az_lo = a.az_lo;
+    P.az_hi = a.az_hi;
+    P.ah_z0 = a.ah_z0;
+    P.aw = a.aw;
+    P.ah = a.ah;
+    P.NA = a.NA;
+    P.a_head0 = a.a_head0;
     return P;
 }
 
@@ -1140,6 +1235,24 @@ char *pops_at(lb_handle *h, int which)
     return h->ws + h->L.pops + which * al(pop_set_bytes(h->P.N, h->p.storage, lattice_q(h->p)));
 }
 
+// The read-out's full-box masses (2N doubles) and momentum (3N values) at
+// cell indices: in the spare population buffer after the staged outputs
+// (D3Q19; its size, 2 x 19 values or 19 words per cell, exceeds the 68 bytes
+// per cell this takes at most), or the boundary-only arrays themselves
+// (D2Q9, full-box there).
+double *ro_momd(lb_handle *h)
+{
+    if (is_d2(h->p)) return as<double>(h, h->L.momd);
+    return reinterpret_cast<double *>(pops_at(h, 1 - h->cur) + h->L.ro);
+}
+
+template <typename R>
+R *ro_mom(lb_handle *h)
+{
+    if (is_d2(h->p)) return as<R>(h, h->L.mom);
+    return reinterpret_cast<R *>(pops_at(h, 1 - h->cur) + h->L.ro + al(2 * (size_t)h->P.N * 8));
+}
+
 float *mo_at(lb_handle *h, int which)
 {
     if (!reduced(h->p.storage)) return nullptr;
@@ -1175,7 +1288,7 @@ lb_status launch_clock(lb_handle *h)
 template <typename R>
 R *mac_at(lb_handle *h, long t)
 {
-    return as<R>(h, h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.N * sizeof(R)));
+    return as<R>(h, h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.NA * sizeof(R)));
 }
 
 // Where one read-out keeps its per-call partial sums: the pending boundary
@@ -1205,7 +1318,7 @@ lb_status run_readout(lb_handle *h, const ReadSlots &S, int &nbsp)
                            as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pend, h->first, 1);
     else
         hipLaunchKernelGGL((k_moments<R, ST>), dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
-                           pop_src<R, ST>(h, h->cur), mac_at<R>(h, h->t - 1), as<double>(h, L.momd), as<R>(h, L.mom),
+                           pop_src<R, ST>(h, h->cur), mac_at<R>(h, h->t - 1), ro_momd(h), ro_mom<R>(h),
                            as<R>(h, L.chi), S.pend, h->first);
     if (lb_status s = check_launch(h, "k_moments")) return s;
     if (h->p.has_nozzle && !h->first) {
@@ -1213,8 +1326,8 @@ lb_status run_readout(lb_handle *h, const ReadSlots &S, int &nbsp)
             hipLaunchKernelGGL(lbk2::k2_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
                                as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pendc, 0);
         else
-            hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h),
-                               as<double>(h, L.momd), as<R>(h, L.mom), as<R>(h, L.chi), S.pendc, 0);
+            hipLaunchKernelGGL(k_create<R>, dim3(L.nb_create), dim3(TPB), 0, h->stream, h->P, geo(h), ro_momd(h),
+                               ro_mom<R>(h), as<R>(h, L.chi), S.pendc, 0);
         if (lb_status s = check_launch(h, "k_create")) return s;
         nbsp = S.zero_pendc ? NB_SPARSE : (int)L.nb_create;
     } else if (S.zero_pendc) {
@@ -1412,7 +1525,7 @@ template <typename R, typename O>
 lb_status run_output(lb_handle *h, const ReadSlots &S, O *ry, O *rb, O *u)
 {
     hipLaunchKernelGGL((k_output<R, O>), dim3(S.nb), dim3(TPB), 0, h->stream, h->P, geo(h),
-                       as<double>(h, h->L.momd), as<R>(h, h->L.mom), ry, rb, u, S.part);
+                       ro_momd(h), ro_mom<R>(h), ry, rb, u, S.part);
     return check_launch(h, "k_output");
 }
 
@@ -1755,7 +1868,7 @@ lb_status batch_capture(lb_batch *b, int k)
 
 void *mac_ptr(lb_handle *h, long t)
 {
-    return h->ws + h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.N * real_size(h->p.storage));
+    return h->ws + h->L.mac + (t & 1) * al(NMAC * (size_t)h->P.NA * real_size(h->p.storage));
 }
 
 // A handle's slot: its buffers for the steps of parity q = 0, 1 counted from
@@ -1948,7 +2061,7 @@ lb_status lb_observe(lb_handle *h, const lb_window *w, lb_observables *out)
     // the section's cells, at most one block per 256 (the read-out's part
     // slots hold one entry per 256 cells of the box)
     const int nb = (int)std::min<long long>(((long long)nx * nz + TPB - 1) / TPB, 1024);
-    hipLaunchKernelGGL(k_observe, dim3(nb), dim3(TPB), 0, h->stream, h->P, geo(h), as<double>(h, h->L.momd), x_lo,
+    hipLaunchKernelGGL(k_observe, dim3(nb), dim3(TPB), 0, h->stream, h->P, geo(h), ro_momd(h), x_lo,
                        w->x_len, w->z_hi, w->y, S.part);
     hipLaunchKernelGGL(k_observe_final, dim3(1), dim3(TPB), 0, h->stream, S.part, nb, S.red);
     if (lb_status s = check_launch(h, "k_observe")) return s;

@@ -150,6 +150,47 @@ def test_printing_small_box(G, printing_oracle, storage):
     assert sim.t == checks[-1]
 
 
+def window_case(storage):
+    cfg = W.printing((72, 40, 20), head_x0=(50.0, 30.5), r_in=3.0, tip_z=7.0, head_v=(0.05, 0.03), u_ink=0.02,
+                     n=0.5, storage=storage)
+    ry, rb = W.nozzle_fields(cfg)
+    return cfg, ry, rb
+
+
+@pytest.fixture(scope="module")
+def window_oracle(O):
+    cfg, ry, rb = window_case("f64")
+    s = O.OracleSim(cfg, ry, rb)
+    out = {}
+    for t in (200, 600):
+        s.step(t - s.t)
+        out[t] = s.moments()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_head_crossing_the_compact_window(G, window_oracle, storage):
+    """The boundary-only arrays keep the head region's columns modulo a
+    window: the smallest divisor of the extent of at least 2 ceil(r_out) + 16
+    = 26 columns (r_out = 5), 36 of 72 in x and 40 (the whole extent) in y.
+    A head moving at (0.05, 0.03) for 600 steps from (50, 30.5) crosses the
+    x window and the periodic boundaries in x and y, so slots are reused by
+    cells 36 columns apart while the head's neighbourhood moves through
+    them: fields and the FP64 mass ledger against the oracle.  (A window
+    that does not divide the extent would alias cells across the periodic
+    boundary.)"""
+    cfg, ry, rb = window_case(storage)
+    sim = G.Sim(cfg, ry, rb)
+    for t in (200, 600):
+        sim.step(t - sim.t)
+        g, o = sim.moments(), window_oracle[t]
+        compare(g, o, TOL[storage], f"window crossing {storage} t={t}")
+        ledger_tol = 1e-9 if storage == "f64" else 1e-5
+        for key in ("mass", "mass_wall", "mass_open", "mass_created", "mass_deleted"):
+            scale = max(1.0, np.abs(o[3]["mass"]).max() * 1e-6)
+            assert np.abs(g[3][key] - o[3][key]).max() <= ledger_tol * max(np.abs(o[3][key]).max(), scale), key
+
+
 # ------------------------------------------------- nozzle extrusion (1000)
 
 @pytest.mark.slow

@@ -43,3 +43,26 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_footprint_keeps_boundary_arrays_compact(lib):
+    """The boundary-only arrays (moment sets, colour fields, macro fields) of
+    a walled D3Q19 box hold the z faces' layers and a window around the head,
+    not the whole box: the 1024x512x384 BF16-deviation domain needs little
+    more than its population state (2 x (19 words + 5 FP32 moments) per cell,
+    padded), the 512x256x128 FP32 print bed little more than its 2 x 38
+    planes; a periodic box keeps one slot per cell."""
+    big = W.largest_domain("bf16dev")
+    N = 1024 * 512 * 384
+    state = 2 * 19 * (4 * N + (1 << 20) + 256) + 2 * 5 * (4 * N + (1 << 20) + 256)
+    fp = LB.footprint(big)
+    assert state <= fp <= 40e9, fp
+    assert fp - state < 0.05 * state, (fp, state)
+    bed = W.print_bed(storage="f32")
+    n = 512 * 256 * 128
+    pops = 2 * 38 * (4 * n + (1 << 20) + 256)
+    assert LB.footprint(bed) - pops < 0.05 * pops
+    # periodic droplet: every cell keeps its slots (no faces, no head)
+    cfg, _, _ = W.static_droplet(storage="f32")
+    m = 32 ** 3
+    assert LB.footprint(cfg) >= 2 * 38 * (4 * m + 256) + m * (16 + 60 + 12 + 40)
