@@ -314,11 +314,14 @@ __device__ __forceinline__ void feq_TY(const DevParams &P, float rY, float rB, f
     if (X) cu = X > 0 ? ux : -ux;
     if (Yc) cu = cu + (Yc > 0 ? uy : -uy);
     if (Z) cu = cu + (Z > 0 ? uz : -uz);
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float E = w * (3.f * cu + 4.5f * (cu * cu) - 1.5f * uu);
+    // explicit fused multiply-adds: the same instructions wherever it is
+    // inlined (encoder and decoders agree bit for bit)
+    const float uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    const float E = w * __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.f), -1.5f * uu);
     const float rho = rY + rB;
     fY = rY * (float(P.phi[0][S]) + E);
-    fT = rY * float(P.phid[0][S]) + rB * float(P.phid[1][S]) + (rho - float(P.rho_ref)) * w + rho * E;
+    fT = __builtin_fmaf(rY, float(P.phid[0][S]),
+                        __builtin_fmaf(rB, float(P.phid[1][S]), __builtin_fmaf(rho - float(P.rho_ref), w, rho * E)));
 }
 
 // Read access to the post-collision populations of step t-1: the reduced
