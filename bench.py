@@ -11,8 +11,10 @@ over the timed region; beside it the rate of a plain 1 GiB copy on the same
 GPU) and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
 Other modes: --workload largest (the 1024x512x384 domain, BF16 deviations by
-default) and --serve (the parameter-sweep trace through the continuous-
-batching server and one request at a time).
+default), --workload print2d (the paper's 2-D printing set-up on D2Q9, swept
+over the nozzle speed, with the Sec. IV observables) and --serve (the
+parameter-sweep trace through the continuous-batching server and one request
+at a time).
 """
 from __future__ import annotations
 
@@ -287,6 +289,67 @@ def largest(args):
     print(json.dumps(out), flush=True)
 
 
+def print2d(args):
+    """The paper's 2-D printing set-up (Sec. III, 880 x 240 D2Q9, one Table I
+    ink) swept over the nozzle speed v_nozzle = ratio * v_ink: each run lets
+    the ink cross the gap to the substrate and the nozzle travel `travel`
+    nozzle widths, then reads the Sec. IV observables of the thread behind
+    the nozzle (lb_observe) and forms the POI, normalised over the sweep."""
+    import math
+
+    import torch
+
+    from paper_2102_02655_amd import lbprint, workloads as W
+
+    st = args.storage or "f32"
+    d, gap, wall, nx, nz = 60.0, 60.0, 4.0, 880, 240
+    v_ink = W.ink_speed_lb(args.ink)
+    runs, total_lu, total_s = [], 0, 0.0
+    for r in [float(v) for v in args.ratios.split(",")]:
+        cfg = W.printing_2d(args.ink, v_ratio=r, nx=nx, nz=nz, d=d, gap=gap, wall=wall, storage=st)
+        ry, rb = W.nozzle_fields(cfg)
+        steps = int(math.ceil(gap / v_ink + args.travel * d / (r * v_ink)))
+        sim = lbprint.Sim(cfg, ry, rb, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, chunk = 0, 20000
+        while done < steps:
+            k = min(chunk, steps - done)
+            sim.step(k)
+            done += k
+            torch.cuda.synchronize()
+            print(f"print2d {args.ink} v_nozzle = {r} v_ink: {done}/{steps} steps", file=sys.stderr, flush=True)
+        dt = time.perf_counter() - t0
+        # the thread: the columns the bore has swept, from the nozzle's start
+        # to its position now (the head moves towards -x), below the tip
+        x_start = cfg["nozzle"]["x0"][0]
+        x_now = x_start - r * v_ink * steps
+        lo = int(math.floor(x_now - d / 2.0))
+        length = int(math.ceil(x_start + d / 2.0)) - lo + 1
+        obs = sim.observe(lo % nx, min(length, nx), int(gap))
+        _, _, _, cons = sim.moments(dtype="float32")
+        sim.close()
+        poi = (obs["coverage"] * d / (obs["height"] * obs["dp_max"])
+               if obs["height"] > 0 and obs["dp_max"] > 0 else 0.0)
+        total_lu += nx * nz * steps
+        total_s += dt
+        runs.append({"v_ratio": r, "steps": steps, "seconds": dt, "MLUPS": nx * nz * steps / dt / 1e6,
+                     "height": obs["height"], "coverage": obs["coverage"], "ink_area": obs["ink_area"],
+                     "dp_max_over_p0": obs["dp_max"] / obs["p0"], "substrate_ink": obs["substrate_ink"],
+                     "POI": poi, "mass": list(map(float, cons["mass"]))})
+    top = max((x["POI"] for x in runs), default=0.0)
+    for x in runs:
+        x["POI_norm"] = x["POI"] / top if top > 0 else 0.0
+    out = {"metric": "MLUPS", "value": total_lu / total_s / 1e6, "unit": "MLUPS", "n_gpus": 1,
+           "higher_is_better": True, "vs_baseline": None, "dtype": "f64" if st == "f64" else "f32",
+           "data": "synthetic",
+           "config": {"workload": f"2-D printing sweep (Sec. III set-up), D2Q9 {nx}x{nz}, ink {args.ink}, "
+                                  f"nozzle travel {args.travel} d after the ink crosses the gap",
+                      "storage": st, "v_ink": v_ink},
+           "runs": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,8 +357,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default=None, choices=["f32", "f64", "bf16dev", "f16dev"],
                     help="population storage (default: f32 on the print bed, bf16dev on the largest domain)")
-    ap.add_argument("--workload", default="print_bed", choices=["print_bed", "largest"],
-                    help="print_bed: the 512x256x128 benchmark; largest: the 1024x512x384 domain")
+    ap.add_argument("--workload", default="print_bed", choices=["print_bed", "largest", "print2d"],
+                    help="print_bed: the 512x256x128 benchmark; largest: the 1024x512x384 domain; "
+                         "print2d: the paper's 2-D printing sweep over the nozzle speed")
+    ap.add_argument("--ink", default="1%-25C", help="print2d: Table I ink")
+    ap.add_argument("--ratios", default="0.25,0.5,0.75,1.0,1.25,1.5,1.75",
+                    help="print2d: nozzle speeds in units of the ink speed")
+    ap.add_argument("--travel", type=float, default=2.0, help="print2d: nozzle travel in nozzle widths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle on 20 steps of the whole 512x256x128 box (about 15 GB of host memory)")
@@ -320,6 +388,9 @@ def main():
         return
     if args.workload == "largest":
         largest(args)
+        return
+    if args.workload == "print2d":
+        print2d(args)
         return
     if args.storage is None:
         args.storage = "f32"
