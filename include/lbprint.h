@@ -129,8 +129,9 @@ typedef struct lb_handle lb_handle;
  * boundary-only arrays (moment sets, colour fields and macro fields of the
  * cells next to the z faces and the head), which a D3Q19 box with z walls
  * keeps for three layers at each face and a window of columns around the
- * head (the smallest divisor of nx, resp. ny, of at least 2 ceil(r_out) + 16;
- * head speed at most 1/2 per step), and
+ * head (the smallest power of two dividing nx, resp. ny, of at least
+ * 2 ceil(r_out) + 16, else the whole extent; head speed at most 1/2 per
+ * step), and
  * a periodic box, a faster head or a D2Q9 box for every cell.  LB_EINVAL on
  * bad parameters. */
 lb_status lb_footprint(const lb_params *p, size_t *bytes);

@@ -82,6 +82,7 @@ struct DevParams {
     // modulo (aw, ah) from a_head0 on; slot NA - 1 is a sink for cells
     // outside both (never used by a correct step).
     int aux, az_lo, az_hi, ah_z0, aw, ah;
+    int amx, amy;  // column masks of the window: aw - 1 (a power of two) or all ones (aw = nx)
     long long NA, a_head0;
 };
 
@@ -93,21 +94,20 @@ struct HeadPos {
 __device__ __forceinline__ int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // Slot of cell (x, y, z) (inside the box) in the boundary-only arrays.  The
-// head region's window (aw x ah columns) is wider than every set of cells a
-// step or two consecutive steps touch around the head axis (the head box,
-// its neighbours, the macro fields written for the next step), so no two
-// cells in use at once share a slot.
+// head region's window (aw x ah columns, each a power of two dividing the
+// box extent, or the extent itself) is wider than every set of cells a step
+// or two consecutive steps touch around the head axis (the head box, its
+// neighbours, the macro fields written for the next step), so no two cells
+// in use at once share a slot.  Straight-line code: it is inlined at every
+// boundary rule's neighbour reads.
 __host__ __device__ inline long long aidx(const DevParams &P, int x, int y, int z)
 {
     const long long pl = (long long)P.nx * P.ny;
     if (!P.aux) return (long long)z * pl + (long long)y * P.nx + x;
     if (z < P.az_lo) return (long long)z * pl + (long long)y * P.nx + x;
     if (z >= P.nz - P.az_hi) return (long long)(P.az_lo + z - (P.nz - P.az_hi)) * pl + (long long)y * P.nx + x;
-    if (z < P.ah_z0 || !P.has_nozzle) return P.NA - 1;
-    // power-of-two windows (the usual case) by mask
-    const int xm = (P.aw & (P.aw - 1)) == 0 ? (x & (P.aw - 1)) : x % P.aw;
-    const int ym = (P.ah & (P.ah - 1)) == 0 ? (y & (P.ah - 1)) : y % P.ah;
-    return P.a_head0 + ((long long)(z - P.ah_z0) * P.ah + ym) * P.aw + xm;
+    if (z < P.ah_z0) return P.NA - 1;
+    return P.a_head0 + ((long long)(z - P.ah_z0) * P.ah + (y & P.amy)) * P.aw + (x & P.amx);
 }
 
 // ---------------------------------------------------------------- geometry

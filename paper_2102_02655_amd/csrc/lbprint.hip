@@ -797,7 +797,7 @@ __global__ __launch_bounds__(TPB) void kb_pre(const BatchTable *__restrict__ T, 
     const BatchSlot &S = T->slot[m];
     if (j >= S.nsteps) return;
     const int q = j & 1;
-    const DevParams P = S.P;
+    const DevParams &P = S.P;  // fields read from the table on demand (scalar loads)
     pre_body<R, ST>(P, S.G, batch_src<R, ST>(S, q), static_cast<const R *>(S.mac_prev[q]), S.momd,
                     static_cast<R *>(S.mom), static_cast<R *>(S.chi), S.cumpre, 0, blockIdx.x - S.off[BK_PRE], S.nb[BK_PRE]);
 }
@@ -809,7 +809,7 @@ __global__ __launch_bounds__(TPB) void kb_create(const BatchTable *__restrict__ 
     if (m < 0) return;
     const BatchSlot &S = T->slot[m];
     if (j >= S.nsteps) return;
-    const DevParams P = S.P;
+    const DevParams &P = S.P;  // fields read from the table on demand (scalar loads)
     create_body<R>(P, S.G, S.momd, static_cast<R *>(S.mom), static_cast<R *>(S.chi), S.cumc, 1,
                    blockIdx.x - S.off[BK_CREATE], S.nb[BK_CREATE]);
 }
@@ -821,7 +821,7 @@ __global__ __launch_bounds__(TPB) void kb_wall(const BatchTable *__restrict__ T,
     if (m < 0) return;
     const BatchSlot &S = T->slot[m];
     if (j >= S.nsteps) return;
-    const DevParams P = S.P;
+    const DevParams &P = S.P;  // fields read from the table on demand (scalar loads)
     wall_body<R>(P, S.G, S.momd, static_cast<R *>(S.chi), blockIdx.x - S.off[BK_WALL], S.nb[BK_WALL]);
 }
 
@@ -832,7 +832,7 @@ __global__ __launch_bounds__(TPB) void kb_ghost(const BatchTable *__restrict__ T
     if (m < 0) return;
     const BatchSlot &S = T->slot[m];
     if (j >= S.nsteps) return;
-    const DevParams P = S.P;
+    const DevParams &P = S.P;  // fields read from the table on demand (scalar loads)
     ghost_body<R>(P, S.G, S.momd, static_cast<R *>(S.ghost), blockIdx.x - S.off[BK_GHOST]);
 }
 
@@ -906,15 +906,16 @@ FusedGrid fused_grid(const lb_params &p, int ty, long long want_blocks = 512)
 // within r_out + 4 of the axis for the next step, which reads them around
 // the next position: at most 2 ceil(r_out) + 12 consecutive columns over two
 // steps of a head moving at most half a cell per step.  The window is the
-// smallest divisor of the box's extent that is at least 2 ceil(r_out) + 16
-// (the extent itself if there is none), so that columns sharing a slot are
-// a whole number of windows apart also across the periodic boundary.
-// Periodic boxes, faster heads and boxes the compact form would not shrink
-// keep one slot per cell.
+// smallest power of two dividing the box's extent that is at least
+// 2 ceil(r_out) + 16 (the extent itself if there is none), so that columns
+// sharing a slot are a whole number of windows apart also across the
+// periodic boundary, and a column's place in it is a mask.  Periodic boxes,
+// faster heads and boxes the compact form would not shrink keep one slot per
+// cell.
 int window_of(int extent, int need)
 {
-    for (int d = need; d < extent; ++d)
-        if (extent % d == 0) return d;
+    for (int d = 1; d < extent; d *= 2)
+        if (d >= need && extent % d == 0) return d;
     return extent;
 }
 
@@ -1155,6 +1156,8 @@ DevParams make_dev(const lb_params &p)
     P.ah_z0 = a.ah_z0;
     P.aw = a.aw;
     P.ah = a.ah;
+    P.amx = a.aw == p.nx ? -1 : a.aw - 1;
+    P.amy = a.ah == p.ny ? -1 : a.ah - 1;
     P.NA = a.NA;
     P.a_head0 = a.a_head0;
     return P;

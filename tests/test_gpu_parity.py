@@ -151,7 +151,7 @@ def test_printing_small_box(G, printing_oracle, storage):
 
 
 def window_case(storage):
-    cfg = W.printing((72, 40, 20), head_x0=(50.0, 30.5), r_in=3.0, tip_z=7.0, head_v=(0.05, 0.03), u_ink=0.02,
+    cfg = W.printing((96, 40, 20), head_x0=(74.0, 30.5), r_in=3.0, tip_z=7.0, head_v=(0.05, 0.03), u_ink=0.02,
                      n=0.5, storage=storage)
     ry, rb = W.nozzle_fields(cfg)
     return cfg, ry, rb
@@ -171,11 +171,12 @@ def window_oracle(O):
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_head_crossing_the_compact_window(G, window_oracle, storage):
     """The boundary-only arrays keep the head region's columns modulo a
-    window: the smallest divisor of the extent of at least 2 ceil(r_out) + 16
-    = 26 columns (r_out = 5), 36 of 72 in x and 40 (the whole extent) in y.
-    A head moving at (0.05, 0.03) for 600 steps from (50, 30.5) crosses the
+    window: the smallest power of two dividing the extent of at least
+    2 ceil(r_out) + 16 = 26 columns (r_out = 5), 32 of 96 in x and 40 (the
+    whole extent) in y.
+    A head moving at (0.05, 0.03) for 600 steps from (74, 30.5) crosses the
     x window and the periodic boundaries in x and y, so slots are reused by
-    cells 36 columns apart while the head's neighbourhood moves through
+    cells 32 columns apart while the head's neighbourhood moves through
     them: fields and the FP64 mass ledger against the oracle.  (A window
     that does not divide the extent would alias cells across the periodic
     boundary.)"""
