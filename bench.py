@@ -320,12 +320,14 @@ def print2d(args):
             torch.cuda.synchronize()
             print(f"print2d {args.ink} v_nozzle = {r} v_ink: {done}/{steps} steps", file=sys.stderr, flush=True)
         dt = time.perf_counter() - t0
-        # the thread: the columns the bore has swept, from the nozzle's start
-        # to its position now (the head moves towards -x), below the tip
+        # the thread: the ink deposited behind the nozzle (the head moves
+        # towards -x), from half a nozzle width behind its trailing wall (the
+        # ink still attached to the nozzle left out) back to its start, below
+        # the tip
         x_start = cfg["nozzle"]["x0"][0]
         x_now = x_start - r * v_ink * steps
-        lo = int(math.floor(x_now - d / 2.0))
-        length = int(math.ceil(x_start + d / 2.0)) - lo + 1
+        lo = int(math.ceil(x_now + d + wall))
+        length = int(math.ceil(x_start + d / 2.0 + wall)) - lo + 1
         obs = sim.observe(lo % nx, min(length, nx), int(gap))
         _, _, _, cons = sim.moments(dtype="float32")
         sim.close()
@@ -363,7 +365,7 @@ def main():
     ap.add_argument("--ink", default="1%-25C", help="print2d: Table I ink")
     ap.add_argument("--ratios", default="0.25,0.5,0.75,1.0,1.25,1.5,1.75",
                     help="print2d: nozzle speeds in units of the ink speed")
-    ap.add_argument("--travel", type=float, default=2.0, help="print2d: nozzle travel in nozzle widths")
+    ap.add_argument("--travel", type=float, default=3.0, help="print2d: nozzle travel in nozzle widths")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle on 20 steps of the whole 512x256x128 box (about 15 GB of host memory)")

@@ -164,15 +164,15 @@ __device__ __forceinline__ void store_all(const DevParams &P, const OutCoef<R> &
 // post-collision moments (rho_Y, rho_B, u'), 16-bit (the deviation is the
 // non-equilibrium, perturbation and recolouring part of the compact form).
 template <int ST, int I>
-__device__ __forceinline__ void store_one_dev(const DevParams &P, const LinkSums<float> &L, float rY, float rB,
-                                              float vx, float vy, float vz, gchar *pw, unsigned cellb)
+__device__ __forceinline__ void store_one_dev(const DevParams &P, const LinkSums<float> &L, const EqCell &ec,
+                                              gchar *pw, unsigned cellb)
 {
     typedef __attribute__((address_space(1))) unsigned gU;
     float Tst, cgw;
     link_value<float, I>(L, Tst, cgw);
     const float Yst = float(__builtin_fma(L.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
     float fT, fY;
-    feq_TY<I>(P, rY, rB, vx, vy, vz, fT, fY);
+    feq_TY_cell<I>(P, ec, fT, fY);
     const unsigned wd = (unsigned)encode_dev<ST, I>(Tst - fT) | ((unsigned)encode_dev<ST, I>(Yst - fY) << 16);
     __builtin_nontemporal_store(wd, reinterpret_cast<gU *>(pw + cellb));
 }
@@ -182,9 +182,10 @@ __device__ __forceinline__ void store_all_dev(const DevParams &P, const OutCoef<
                                               float vx, float vy, float vz, gchar *base, unsigned long long pstride,
                                               unsigned cellb)
 {
+    const EqCell ec = eq_cell(rY, rB, vx, vy, vz);
     const LinkSums<float> L = link_sums(K);
     [&]<int... I>(std::integer_sequence<int, I...>) {
-        ((store_one_dev<ST, I>(P, L, rY, rB, vx, vy, vz, base + (unsigned long long)I * pstride, cellb)), ...);
+        ((store_one_dev<ST, I>(P, L, ec, base + (unsigned long long)I * pstride, cellb)), ...);
     }(std::make_integer_sequence<int, lbq::Q>{});
 }
 

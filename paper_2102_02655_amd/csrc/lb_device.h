@@ -302,26 +302,50 @@ __device__ __forceinline__ float decode_dev(unsigned short h)
 }
 
 // Equilibrium of link I for moments (rho_Y, rho_B, u), in the stored bases:
-// T = f^eq - w_I rho_ref (both colours), Y = f^{Y,eq}.
+// T = f^eq - w_I rho_ref (both colours), Y = f^{Y,eq}.  The cell's terms
+// common to all links (rho = rho_Y + rho_B and k = 3/2 u.u) are formed once
+// (EqCell); explicit fused multiply-adds make the result the same
+// instructions wherever it is inlined (encoder and decoders agree bit for
+// bit).
+struct EqCell {
+    float rY, rB, rho, ux, uy, uz, k;
+};
+
+__device__ __forceinline__ EqCell eq_cell(float rY, float rB, float ux, float uy, float uz)
+{
+#pragma clang fp contract(off)
+    EqCell c;
+    c.rY = rY;
+    c.rB = rB;
+    c.rho = rY + rB;
+    c.ux = ux;
+    c.uy = uy;
+    c.uz = uz;
+    c.k = 1.5f * __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    return c;
+}
+
 template <int I>
-__device__ __forceinline__ void feq_TY(const DevParams &P, float rY, float rB, float ux, float uy, float uz,
-                                       float &fT, float &fY)
+__device__ __forceinline__ void feq_TY_cell(const DevParams &P, const EqCell &c, float &fT, float &fY)
 {
 #pragma clang fp contract(off)
     constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I), S = lbq::shell(I);
     const float w = float(lbq::w(I));
     float cu = 0.f;
-    if (X) cu = X > 0 ? ux : -ux;
-    if (Yc) cu = cu + (Yc > 0 ? uy : -uy);
-    if (Z) cu = cu + (Z > 0 ? uz : -uz);
-    // explicit fused multiply-adds: the same instructions wherever it is
-    // inlined (encoder and decoders agree bit for bit)
-    const float uu = __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
-    const float E = w * __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.f), -1.5f * uu);
-    const float rho = rY + rB;
-    fY = rY * (float(P.phi[0][S]) + E);
-    fT = __builtin_fmaf(rY, float(P.phid[0][S]),
-                        __builtin_fmaf(rB, float(P.phid[1][S]), __builtin_fmaf(rho - float(P.rho_ref), w, rho * E)));
+    if (X) cu = X > 0 ? c.ux : -c.ux;
+    if (Yc) cu = cu + (Yc > 0 ? c.uy : -c.uy);
+    if (Z) cu = cu + (Z > 0 ? c.uz : -c.uz);
+    const float E = w * __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.f), -c.k);
+    fY = c.rY * (float(P.phi[0][S]) + E);
+    fT = __builtin_fmaf(c.rY, float(P.phid[0][S]),
+                        __builtin_fmaf(c.rB, float(P.phid[1][S]), __builtin_fmaf(c.rho - float(P.rho_ref), w, c.rho * E)));
+}
+
+template <int I>
+__device__ __forceinline__ void feq_TY(const DevParams &P, float rY, float rB, float ux, float uy, float uz,
+                                       float &fT, float &fY)
+{
+    feq_TY_cell<I>(P, eq_cell(rY, rB, ux, uy, uz), fT, fY);
 }
 
 // Read access to the post-collision populations of step t-1: the reduced

@@ -130,12 +130,6 @@ __device__ __forceinline__ bool in_box(const DevParams &P, const Box3 &B, int x,
     return dx < B.w && dy < B.h && z >= B.z0 && z < B.z0 + B.d;
 }
 
-__device__ __forceinline__ bool prepared(const DevParams &P, const Box3 &head, int x, int y, int z)
-{
-    if (!P.periodic_z && (z == 0 || z == P.nz - 1)) return true;
-    return in_box(P, head, x, y, z);
-}
-
 __device__ __forceinline__ int wrap_any(int a, int n)
 {
     int r = a % n;
@@ -403,7 +397,10 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     constexpr int MW = 68, MH = TY + 4, MR = MW * MH;  // moment region: x0-2 .. x0+65, y0-2 .. y0+TY+1
     constexpr bool DEEP = sizeof(R) == 4;
-    __shared__ float mring[ST == ST_PLAIN ? 1 : 4][NMO][ST == ST_PLAIN ? 1 : MR];
+    // the ring keeps each source cell's equilibrium terms (EqCell: rho_Y,
+    // rho_B, rho, u, 3/2 u.u), formed once per cell as it is written
+    constexpr int NEQ = 7;
+    __shared__ float mring[ST == ST_PLAIN ? 1 : 4][NEQ][ST == ST_PLAIN ? 1 : MR];
     const HeadPos H = G->H;
     const Box3 head = G->bx[0];
     // the last kernel of the step advances the device step counter (the
@@ -607,9 +604,16 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
                 const int k = threadIdx.x + r * (TY + 3) * 64;
-                if (k < MR)
-#pragma unroll
-                    for (int m = 0; m < NMO; ++m) mring[q & 3][m][k] = mreg[r][m];
+                if (k < MR) {
+                    const EqCell ec = eq_cell(mreg[r][0], mreg[r][1], mreg[r][2], mreg[r][3], mreg[r][4]);
+                    mring[q & 3][0][k] = ec.rY;
+                    mring[q & 3][1][k] = ec.rB;
+                    mring[q & 3][2][k] = ec.rho;
+                    mring[q & 3][3][k] = ec.ux;
+                    mring[q & 3][4][k] = ec.uy;
+                    mring[q & 3][5][k] = ec.uz;
+                    mring[q & 3][6][k] = ec.k;
+                }
             }
         }
     };
@@ -623,7 +627,9 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
             const int sl = FIRST ? (p & 3) : ((p - Z) & 3);
             const int k = FIRST ? (ly + 2) * MW + lx + 2 : (ly + 2 - Yc) * MW + lx + 2 - X;
             float fT, fY;
-            feq_TY<I>(P, mring[sl][0][k], mring[sl][1][k], mring[sl][2][k], mring[sl][3][k], mring[sl][4][k], fT, fY);
+            const EqCell ec{mring[sl][0][k], mring[sl][1][k], mring[sl][2][k], mring[sl][3][k],
+                            mring[sl][4][k], mring[sl][5][k], mring[sl][6][k]};
+            feq_TY_cell<I>(P, ec, fT, fY);
             T = fT + decode_dev<ST, I>((unsigned short)(vT & 0xFFFFu));
             Y = fY + decode_dev<ST, I>((unsigned short)(vT >> 16));
         }
