@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # once and written once; the reduced forms also read and write the cell's
 # five FP32 moments (2 x (38 x 2 + 5 x 4) B).
 BYTES_PER_LU = {"f64": 608, "f32": 304, "bf16dev": 192, "f16dev": 192}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_pc_print_bed_512x256x128_f32_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_pc_print_bed_512x256x128_{}_traffic.md")
 
 
 def source_digest() -> str:
@@ -51,11 +51,13 @@ def source_digest() -> str:
 
 
 def measured_traffic(storage: str):
-    """HBM bytes per launch of the fused kernel from the committed PMC
-    summary, or None when the kernel sources changed since it was taken."""
-    if storage != "f32" or not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes per launch of the fused kernel on the print bed from the
+    committed PMC summary of this storage form, or None when there is none or
+    the kernel sources changed since it was taken."""
+    path = TRAFFIC_FILE.format(storage)
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     m_b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not (m_sha and m_b) or m_sha.group(1) != source_digest():
