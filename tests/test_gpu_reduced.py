@@ -156,3 +156,69 @@ def test_storage_forms_print_bed_crop(n):
         s.close()
         for e, b in zip(errs, CROP_BOUND[st]):
             assert e <= b, (st, errs, CROP_BOUND[st])
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_largest_domain_first_steps_against_an_oracle_crop():
+    """The 1024x512x384 domain (BF16 deviations, the largest-domain
+    benchmark's launch configuration: compact boundary arrays, 39.9 GB)
+    against the oracle where it can follow: the state starts as pure air at
+    rest outside the ink-filled bore, an exact fixed point of the step away
+    from the head, and a step moves a disturbance at most two cells (pull and
+    colour stencil).  After three steps the box therefore equals, cell for
+    cell, a 128x128x384 crop centred on the head with the same walls, top
+    face and nozzle, which the FP64 oracle runs (its disturbance reaches
+    31 cells from the axis; beyond, both hold air at rest to rounding).
+    Also: the far field is at rest on the GPU, and the FP64 mass ledger
+    closes."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2102_02655_amd import lbprint as LB
+
+    cfg = W.largest_domain("bf16dev")
+    nx, ny, nz = cfg["shape"]
+    N = nx * ny * nz
+    fp = LB.footprint(cfg)
+    assert fp <= 40e9, fp
+    ry, rb = W.nozzle_fields(cfg)
+    sim = LB.Sim(cfg, ry, rb)
+    del ry, rb
+    c0 = sim.moments_device(None, None, None)
+    sim.step(3)
+    dev = torch.device("cuda:0")
+    gy = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+    gb = torch.empty_like(gy)
+    gu = torch.empty((nz, ny, nx, 3), dtype=torch.float32, device=dev)
+    c1 = sim.moments_device(gy, gb, gu)
+    sim.close()
+    # the ledger: mass change = wall + open + created - deleted
+    for k in range(2):
+        lhs = c1["mass"][k] - c0["mass"][k]
+        rhs = c1["mass_wall"][k] + c1["mass_open"][k] + c1["mass_created"][k] - c1["mass_deleted"][k]
+        assert abs(lhs - rhs) <= 1e-9 * c1["mass"][1], (k, lhs, rhs)
+    # the crop around the head axis at (256, 256)
+    x0, y0, w = 256 - 64, 256 - 64, 128
+    far = torch.ones((ny, nx), dtype=torch.bool, device=dev)
+    far[y0:y0 + w, x0:x0 + w] = False
+    assert float((gb[:, far] - 1.0).abs().max()) <= 1e-6 and float(gy[:, far].abs().max()) <= 1e-6
+    assert float(gu[:, far].abs().max()) <= 1e-6
+    g = (gy[:, y0:y0 + w, x0:x0 + w].double().cpu().numpy(), gb[:, y0:y0 + w, x0:x0 + w].double().cpu().numpy(),
+         gu[:, y0:y0 + w, x0:x0 + w].double().cpu().numpy())
+    del gy, gb, gu
+    crop = W.printing((w, w, nz), head_x0=(64.0, 64.0), r_in=24.0, tip_z=48.0, head_v=(0.01, 0.0), u_ink=0.01,
+                      n=0.5, storage="f64")
+    cy, cb = W.nozzle_fields(crop)
+    o = O.OracleSim(crop, cy, cb)
+    o.step(3)
+    ref = o.moments()
+    # the crop's own edge columns are far field too
+    edge = np.ones((w, w), dtype=bool)
+    edge[8:w - 8, 8:w - 8] = False
+    assert np.abs(ref[1][:, edge] - 1.0).max() <= 1e-12 and np.abs(ref[2][:, edge]).max() <= 1e-12
+    errs = (rel(g[0], ref[0]), rel(g[1], ref[1]), rel(g[2], ref[2]))
+    print(f"1024x512x384 bf16dev, 3 steps, crop around the head: rho_Y {errs[0]:.2e} rho_B {errs[1]:.2e} "
+          f"u {errs[2]:.2e}; footprint {fp / 1e9:.2f} GB, {N} cells")
+    for e, b in zip(errs, BOUND["bf16dev"]):
+        assert e <= b, (errs, BOUND["bf16dev"])
