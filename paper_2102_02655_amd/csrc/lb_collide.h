@@ -173,7 +173,8 @@ __device__ __forceinline__ void store_one_dev(const DevParams &P, const LinkSums
     const float Yst = float(__builtin_fma(L.fracY, lbq::w(I) * P.rho_ref + (double)Tst, (double)cgw));
     float fT, fY;
     feq_TY_cell<I>(P, ec, fT, fY);
-    const unsigned wd = (unsigned)encode_dev<ST, I>(Tst - fT) | ((unsigned)encode_dev<ST, I>(Yst - fY) << 16);
+    constexpr float s = eq_scale<I>();  // exact: the deviations are f* - s fT, f* - s fY
+    const unsigned wd = encode_pair<ST, I>(__builtin_fmaf(-s, fT, Tst), __builtin_fmaf(-s, fY, Yst));
     __builtin_nontemporal_store(wd, reinterpret_cast<gU *>(pw + cellb));
 }
 
@@ -182,8 +183,11 @@ __device__ __forceinline__ void store_all_dev(const DevParams &P, const OutCoef<
                                               float vx, float vy, float vz, gchar *base, unsigned long long pstride,
                                               unsigned cellb)
 {
-    const EqCell ec = eq_cell(rY, rB, vx, vy, vz);
+    const EqCell ec = eq_cell(P, rY, rB, vx, vy, vz);
     const LinkSums<float> L = link_sums(K);
+    // an opaque 32-bit offset: every store then takes the scalar-base form
+    // (no 64-bit address arithmetic per store)
+    asm volatile("" : "+v"(cellb));
     [&]<int... I>(std::integer_sequence<int, I...>) {
         ((store_one_dev<ST, I>(P, L, ec, base + (unsigned long long)I * pstride, cellb)), ...);
     }(std::make_integer_sequence<int, lbq::Q>{});

@@ -84,6 +84,9 @@ struct DevParams {
     int aux, az_lo, az_hi, ah_z0, aw, ah;
     int amx, amy;  // column masks of the window: aw - 1 (a power of two) or all ones (aw = nx)
     long long NA, a_head0;
+    // equilibrium coefficients of the reduced storage forms (see EqCell):
+    // phi_1^Y, phi_1^B, w_1 rho_ref, g_Y, g_Y - g_B, g_B
+    float eqf[6];
 };
 
 // Head axis of the previous and the current step, wrapped into the box.
@@ -220,12 +223,14 @@ struct Mom {
     R m[NMOM];
 };
 
+// Sums start at -0, the identity of IEEE addition (+0 is not: -0 + 0 = +0),
+// so the first term costs no addition.
 template <typename R>
 __device__ __forceinline__ void mom_zero(Mom<R> &M)
 {
-    M.dm[0] = M.dm[1] = 0.0;
+    M.dm[0] = M.dm[1] = -0.0;
 #pragma unroll
-    for (int q = 0; q < NMOM; ++q) M.m[q] = R(0);
+    for (int q = 0; q < NMOM; ++q) M.m[q] = R(-0.0);
 }
 
 // Accumulate one pulled population pair.  FULL = false keeps only the two
@@ -254,6 +259,37 @@ __device__ __forceinline__ void mom_add(Mom<R> &M, R T, R Y)
     if (Yc && Z) M.m[16] += Yc * Z > 0 ? Y : -Y;
 }
 
+// Accumulate link I (odd) and its opposite I + 1 together: the odd moments
+// take the pair's difference and the even ones its sum, one addition each
+// instead of two; the masses stay per link (FP64).
+template <typename R, int I, bool FULL = true>
+__device__ __forceinline__ void mom_add_pair(Mom<R> &M, R Ta, R Ya, R Tb, R Yb)
+{
+    static_assert((I & 1) == 1 && lbq::opp(I) == I + 1, "a link and its opposite");
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+    M.dm[0] += (double)Ta;
+    M.dm[1] += (double)Ya;
+    M.dm[0] += (double)Tb;
+    M.dm[1] += (double)Yb;
+    if constexpr (!FULL) return;
+    const R dT = Ta - Tb, sT = Ta + Tb, sY = Ya + Yb;
+    if (X) M.m[2] += X > 0 ? dT : -dT;
+    if (Yc) M.m[3] += Yc > 0 ? dT : -dT;
+    if (Z) M.m[4] += Z > 0 ? dT : -dT;
+    if (X) M.m[5] += sT;
+    if (Yc) M.m[6] += sT;
+    if (Z) M.m[7] += sT;
+    if (X && Yc) M.m[8] += X * Yc > 0 ? sT : -sT;
+    if (X && Z) M.m[9] += X * Z > 0 ? sT : -sT;
+    if (Yc && Z) M.m[10] += Yc * Z > 0 ? sT : -sT;
+    if (X) M.m[11] += sY;
+    if (Yc) M.m[12] += sY;
+    if (Z) M.m[13] += sY;
+    if (X && Yc) M.m[14] += X * Yc > 0 ? sY : -sY;
+    if (X && Z) M.m[15] += X * Z > 0 ? sY : -sY;
+    if (Yc && Z) M.m[16] += Yc * Z > 0 ? sY : -sY;
+}
+
 // Boundary-flux accumulators of one pull (FP64): bounce-back family (Y, B),
 // anti-bounce-back (Y, B).
 struct Flux {
@@ -273,23 +309,23 @@ struct Flux {
 enum { ST_PLAIN = 0, ST_BF16 = 1, ST_F16 = 2 };
 constexpr int NMO = 5;  // stored source moments: rho_Y, rho_B, u'_x, u'_y, u'_z
 
-__device__ __forceinline__ unsigned short enc_bf16(float v)
-{
-    unsigned u = __float_as_uint(v);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (unsigned short)(u >> 16);
-}
 __device__ __forceinline__ float dec_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
-__device__ __forceinline__ unsigned short enc_f16(float v) { return __builtin_bit_cast(unsigned short, (_Float16)v); }
 __device__ __forceinline__ float dec_f16(unsigned short h) { return (float)__builtin_bit_cast(_Float16, h); }
 
+// The stored word of link I: the deviations of set T (low half) and set Y
+// (high half), rounded to nearest even by one packed conversion.
 template <int ST, int I>
-__device__ __forceinline__ unsigned short encode_dev(float d)
+__device__ __forceinline__ unsigned encode_pair(float dT, float dY)
 {
-    if constexpr (ST == ST_BF16)
-        return enc_bf16(d);
-    else
-        return enc_f16(d * float(1.0 / lbq::w(I)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    if constexpr (ST == ST_BF16) {
+        typedef __bf16 h2v __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(unsigned, __builtin_convertvector((f2v{dT, dY}), h2v));
+    } else {
+        typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+        constexpr float k = float(1.0 / lbq::w(I));
+        return __builtin_bit_cast(unsigned, __builtin_convertvector((f2v{dT * k, dY * k}), h2v));
+    }
 }
 
 template <int ST, int I>
@@ -302,50 +338,84 @@ __device__ __forceinline__ float decode_dev(unsigned short h)
 }
 
 // Equilibrium of link I for moments (rho_Y, rho_B, u), in the stored bases:
-// T = f^eq - w_I rho_ref (both colours), Y = f^{Y,eq}.  The cell's terms
-// common to all links (rho = rho_Y + rho_B and k = 3/2 u.u) are formed once
-// (EqCell); explicit fused multiply-adds make the result the same
-// instructions wherever it is inlined (encoder and decoders agree bit for
-// bit).
+// T = f^eq - w_I rho_ref (both colours), Y = f^{Y,eq}.  For a moving link
+// phi_I^k = w_I (1 - alpha_k) / (1 - w_0) (Sec. II.A), so both are w_I / w_1
+// (w_1: the weight of an axis link) times an affine function of
+// q_I = 3 c_I.u + 9/2 (c_I.u)^2 whose coefficients belong to the cell:
+//   T = s_I (t_rho q_I + a_T),   Y = s_I (t_Y q_I + a_Y),   s_I = w_I / w_1,
+//   t_rho = w_1 rho,  t_Y = w_1 rho_Y,  k = 3/2 u.u,
+//   a_T = phi_1^Y rho_Y + phi_1^B rho_B - w_1 (rho_ref + rho k),
+//   a_Y = rho_Y (phi_1^Y - w_1 k).
+// s_I is 1 or 1/2, so the scaling is exact.  The rest link follows from the
+// same coefficients: Y_0 = g_Y t_Y + (w_0 / w_1) a_Y and
+// T_0 = (g_Y - g_B) t_Y + g_B t_rho + (w_0 / w_1) a_T, with
+// g_k = (alpha_k - w_0 phi_1^k / w_1) / w_1 (DevParams::eqf).  A cell's
+// coefficients (EqCell) are formed once; a link then costs a few operations.
+// Explicit fused multiply-adds make the result the same instructions
+// wherever it is inlined (encoder and decoders agree bit for bit).
 struct EqCell {
-    float rY, rB, rho, ux, uy, uz, k;
+    float tr, ty, aT, aY, ux3, uy3, uz3;  // t_rho, t_Y, a_T, a_Y, 3u
 };
 
-__device__ __forceinline__ EqCell eq_cell(float rY, float rB, float ux, float uy, float uz)
+__device__ __forceinline__ EqCell eq_cell(const DevParams &P, float rY, float rB, float ux, float uy, float uz)
 {
 #pragma clang fp contract(off)
+    constexpr float w1 = float(lbq::w_of_shell(1));
     EqCell c;
-    c.rY = rY;
-    c.rB = rB;
-    c.rho = rY + rB;
-    c.ux = ux;
-    c.uy = uy;
-    c.uz = uz;
-    c.k = 1.5f * __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    const float k = 1.5f * __builtin_fmaf(ux, ux, __builtin_fmaf(uy, uy, uz * uz));
+    c.tr = w1 * (rY + rB);
+    c.ty = w1 * rY;
+    c.aT = __builtin_fmaf(-c.tr, k, __builtin_fmaf(rY, P.eqf[0], __builtin_fmaf(rB, P.eqf[1], -P.eqf[2])));
+    c.aY = __builtin_fmaf(-c.ty, k, rY * P.eqf[0]);
+    c.ux3 = 3.f * ux;
+    c.uy3 = 3.f * uy;
+    c.uz3 = 3.f * uz;
     return c;
 }
 
+// s_I of the scaling above
+template <int I>
+constexpr float eq_scale()
+{
+    return I == 0 ? 1.f : float(lbq::w(I) / lbq::w_of_shell(1));
+}
+
+// Link I's equilibrium before the scaling: T = s_I fT, Y = s_I fY.
 template <int I>
 __device__ __forceinline__ void feq_TY_cell(const DevParams &P, const EqCell &c, float &fT, float &fY)
 {
 #pragma clang fp contract(off)
-    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I), S = lbq::shell(I);
-    const float w = float(lbq::w(I));
-    float cu = 0.f;
-    if (X) cu = X > 0 ? c.ux : -c.ux;
-    if (Yc) cu = cu + (Yc > 0 ? c.uy : -c.uy);
-    if (Z) cu = cu + (Z > 0 ? c.uz : -c.uz);
-    const float E = w * __builtin_fmaf(cu, __builtin_fmaf(4.5f, cu, 3.f), -c.k);
-    fY = c.rY * (float(P.phi[0][S]) + E);
-    fT = __builtin_fmaf(c.rY, float(P.phid[0][S]),
-                        __builtin_fmaf(c.rB, float(P.phid[1][S]), __builtin_fmaf(c.rho - float(P.rho_ref), w, c.rho * E)));
+    constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+    if constexpr (I == 0) {
+        constexpr float r0 = float(lbq::w_of_shell(0) / lbq::w_of_shell(1));
+        fY = __builtin_fmaf(c.ty, P.eqf[3], r0 * c.aY);
+        fT = __builtin_fmaf(c.ty, P.eqf[4], __builtin_fmaf(c.tr, P.eqf[5], r0 * c.aT));
+    } else {
+        // c_I . 3u over the nonzero components only (an added 0 would stay:
+        // it is not an identity for -0)
+        const float ax = X > 0 ? c.ux3 : -c.ux3, ay = Yc > 0 ? c.uy3 : -c.uy3, az = Z > 0 ? c.uz3 : -c.uz3;
+        static_assert((X != 0) + (Yc != 0) + (Z != 0) <= 2, "D3Q19 links have at most two components");
+        float cu;
+        if constexpr (X != 0)
+            cu = Yc != 0 ? ax + ay : (Z != 0 ? ax + az : ax);
+        else
+            cu = Yc != 0 ? (Z != 0 ? ay + az : ay) : az;
+        const float q = cu * __builtin_fmaf(0.5f, cu, 1.f);
+        fT = __builtin_fmaf(c.tr, q, c.aT);
+        fY = __builtin_fmaf(c.ty, q, c.aY);
+    }
 }
 
-template <int I>
-__device__ __forceinline__ void feq_TY(const DevParams &P, float rY, float rB, float ux, float uy, float uz,
-                                       float &fT, float &fY)
+// Link I of a cell from its stored word (16-bit deviations: T in the low
+// half, Y in the high half) and its source cell's coefficients.
+template <int ST, int I>
+__device__ __forceinline__ void dec_link(const DevParams &P, const EqCell &c, unsigned w, float &T, float &Y)
 {
-    feq_TY_cell<I>(P, eq_cell(rY, rB, ux, uy, uz), fT, fY);
+    float fT, fY;
+    feq_TY_cell<I>(P, c, fT, fY);
+    constexpr float s = eq_scale<I>();
+    T = __builtin_fmaf(s, fT, decode_dev<ST, I>((unsigned short)(w & 0xFFFFu)));
+    Y = __builtin_fmaf(s, fY, decode_dev<ST, I>((unsigned short)(w >> 16)));
 }
 
 // Read access to the post-collision populations of step t-1: the reduced
@@ -373,10 +443,7 @@ struct PopSrc {
     template <int I>
     __device__ __forceinline__ void finish(const DevParams &P, const Raw &r, float &T, float &Y) const
     {
-        float fT, fY;
-        feq_TY<I>(P, r.m[0], r.m[1], r.m[2], r.m[3], r.m[4], fT, fY);
-        T = fT + decode_dev<ST, I>((unsigned short)(r.w & 0xFFFFu));
-        Y = fY + decode_dev<ST, I>((unsigned short)(r.w >> 16));
+        dec_link<ST, I>(P, eq_cell(P, r.m[0], r.m[1], r.m[2], r.m[3], r.m[4]), r.w, T, Y);
     }
     template <int I>
     __device__ __forceinline__ void get(const DevParams &P, long long cell, float &T, float &Y) const
@@ -612,16 +679,21 @@ __device__ __forceinline__ BulkIdx bulk_index(const DevParams &P, int x, int y, 
     return b;
 }
 
-// mom_add over all links of loaded values, one link at a time: the barrier
-// keeps the scheduler from converting every loaded value to FP64 up front
-// (76 registers) before the mass sums consume them.
+// mom_add over all links of loaded values: the rest link, then one opposite
+// pair at a time (the barrier keeps the scheduler from converting every
+// loaded value to FP64 up front, 76 registers, before the mass sums consume
+// them).
 template <typename R, bool FULL, int I = 0>
 __device__ __forceinline__ void mom_add_all(Mom<R> &M, const R (&vT)[lbq::Q], const R (&vY)[lbq::Q])
 {
-    if constexpr (I < lbq::Q) {
-        mom_add<R, I, FULL>(M, vT[I], vY[I]);
+    if constexpr (I == 0) {
+        mom_add<R, 0, FULL>(M, vT[0], vY[0]);
         __builtin_amdgcn_sched_barrier(0);
-        mom_add_all<R, FULL, I + 1>(M, vT, vY);
+        mom_add_all<R, FULL, 1>(M, vT, vY);
+    } else if constexpr (I < lbq::Q) {
+        mom_add_pair<R, I, FULL>(M, vT[I], vY[I], vT[I + 1], vY[I + 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mom_add_all<R, FULL, I + 2>(M, vT, vY);
     }
 }
 

@@ -397,8 +397,8 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     constexpr int MW = 68, MH = TY + 4, MR = MW * MH;  // moment region: x0-2 .. x0+65, y0-2 .. y0+TY+1
     constexpr bool DEEP = sizeof(R) == 4;
-    // the ring keeps each source cell's equilibrium terms (EqCell: rho_Y,
-    // rho_B, rho, u, 3/2 u.u), formed once per cell as it is written
+    // the ring keeps each source cell's equilibrium coefficients (EqCell:
+    // t_rho, t_Y, a_T, a_Y, 3u), formed once per cell as it is written
     constexpr int NEQ = 7;
     __shared__ float mring[ST == ST_PLAIN ? 1 : 4][NEQ][ST == ST_PLAIN ? 1 : MR];
     const HeadPos H = G->H;
@@ -605,14 +605,14 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
             for (int r = 0; r < 2; ++r) {
                 const int k = threadIdx.x + r * (TY + 3) * 64;
                 if (k < MR) {
-                    const EqCell ec = eq_cell(mreg[r][0], mreg[r][1], mreg[r][2], mreg[r][3], mreg[r][4]);
-                    mring[q & 3][0][k] = ec.rY;
-                    mring[q & 3][1][k] = ec.rB;
-                    mring[q & 3][2][k] = ec.rho;
-                    mring[q & 3][3][k] = ec.ux;
-                    mring[q & 3][4][k] = ec.uy;
-                    mring[q & 3][5][k] = ec.uz;
-                    mring[q & 3][6][k] = ec.k;
+                    const EqCell ec = eq_cell(P, mreg[r][0], mreg[r][1], mreg[r][2], mreg[r][3], mreg[r][4]);
+                    mring[q & 3][0][k] = ec.tr;
+                    mring[q & 3][1][k] = ec.ty;
+                    mring[q & 3][2][k] = ec.aT;
+                    mring[q & 3][3][k] = ec.aY;
+                    mring[q & 3][4][k] = ec.ux3;
+                    mring[q & 3][5][k] = ec.uy3;
+                    mring[q & 3][6][k] = ec.uz3;
                 }
             }
         }
@@ -626,12 +626,9 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
             constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
             const int sl = FIRST ? (p & 3) : ((p - Z) & 3);
             const int k = FIRST ? (ly + 2) * MW + lx + 2 : (ly + 2 - Yc) * MW + lx + 2 - X;
-            float fT, fY;
             const EqCell ec{mring[sl][0][k], mring[sl][1][k], mring[sl][2][k], mring[sl][3][k],
                             mring[sl][4][k], mring[sl][5][k], mring[sl][6][k]};
-            feq_TY_cell<I>(P, ec, fT, fY);
-            T = fT + decode_dev<ST, I>((unsigned short)(vT & 0xFFFFu));
-            Y = fY + decode_dev<ST, I>((unsigned short)(vT >> 16));
+            dec_link<ST, I>(P, ec, vT, T, Y);
         }
     };
 
@@ -670,17 +667,26 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
                 } else {
                     // ring cells need only the two masses (their colour
                     // fields); the branch is uniform per wave
+                    // (the rest link, then one opposite pair at a time)
                     auto decode_all = [&]<bool FULL>() {
-                        [&]<int... I>(std::integer_sequence<int, I...>) {
+                        {
+                            R T, Y;
+                            decode.template operator()<0>(p, vT[0], vY[0], T, Y);
+                            mom_add<R, 0, FULL>(M, T, Y);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                        [&]<int... K>(std::integer_sequence<int, K...>) {
                             (
                                 [&] {
-                                    R T, Y;
-                                    decode.template operator()<I>(p, vT[I], vY[I], T, Y);
-                                    mom_add<R, I, FULL>(M, T, Y);
+                                    constexpr int I = 2 * K + 1;
+                                    R Ta, Ya, Tb, Yb;
+                                    decode.template operator()<I>(p, vT[I], vY[I], Ta, Ya);
+                                    decode.template operator()<I + 1>(p, vT[I + 1], vY[I + 1], Tb, Yb);
+                                    mom_add_pair<R, I, FULL>(M, Ta, Ya, Tb, Yb);
                                     __builtin_amdgcn_sched_barrier(0);
                                 }(),
                                 ...);
-                        }(std::make_integer_sequence<int, lbq::Q>{});
+                        }(std::make_integer_sequence<int, (lbq::Q - 1) / 2>{});
                     };
                     if (wave < TY)
                         decode_all.template operator()<true>();

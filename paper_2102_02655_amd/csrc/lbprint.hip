@@ -1090,6 +1090,18 @@ DevParams make_dev(const lb_params &p)
         }
         P.dcs2[k] = (1.0 - a) * cs2 / (1.0 - w0) - cs2;
     }
+    {
+        // coefficients of the reduced forms' equilibrium (D3Q19 weights)
+        const double v0 = lbq::w_of_shell(0), v1 = lbq::w_of_shell(1);
+        double g[2];
+        for (int k = 0; k < 2; ++k) g[k] = (p.alpha[k] - v0 * (1.0 - p.alpha[k]) / (1.0 - v0)) / v1;
+        P.eqf[0] = float((1.0 - p.alpha[0]) * v1 / (1.0 - v0));
+        P.eqf[1] = float((1.0 - p.alpha[1]) * v1 / (1.0 - v0));
+        P.eqf[2] = float(v1 * P.rho_ref);
+        P.eqf[3] = float(g[0]);
+        P.eqf[4] = float(g[0] - g[1]);
+        P.eqf[5] = float(g[1]);
+    }
     P.A = p.A;
     P.beta = p.beta;
     P.eps2 = p.eps_g * p.eps_g;
