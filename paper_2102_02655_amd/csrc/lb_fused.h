@@ -618,18 +618,14 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
         }
     };
     // decode of link I of the pulled cell at plane p (reduced storage)
-    auto decode = [&]<int I>(int p, E vT, E vY, R &T, R &Y) {
-        if constexpr (ST == ST_PLAIN) {
-            T = vT;
-            Y = vY;
-        } else {
-            constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
-            const int sl = FIRST ? (p & 3) : ((p - Z) & 3);
-            const int k = FIRST ? (ly + 2) * MW + lx + 2 : (ly + 2 - Yc) * MW + lx + 2 - X;
-            const EqCell ec{mring[sl][0][k], mring[sl][1][k], mring[sl][2][k], mring[sl][3][k],
-                            mring[sl][4][k], mring[sl][5][k], mring[sl][6][k]};
-            dec_link<ST, I>(P, ec, vT, T, Y);
-        }
+    // coefficients of link I's source cell for the pulled cell at plane p
+    // (reduced storage)
+    auto coef = [&]<int I>(int p) {
+        constexpr int X = lbq::cx(I), Yc = lbq::cy(I), Z = lbq::cz(I);
+        const int sl = FIRST ? (p & 3) : ((p - Z) & 3);
+        const int k = FIRST ? (ly + 2) * MW + lx + 2 : (ly + 2 - Yc) * MW + lx + 2 - X;
+        return EqCell{mring[sl][0][k], mring[sl][1][k], mring[sl][2][k], mring[sl][3][k],
+                      mring[sl][4][k], mring[sl][5][k], mring[sl][6][k]};
     };
 
     auto reduce = [&](int p, const E(&vT)[lbq::Q], const E(&vY)[lbq::Q]) {
@@ -665,13 +661,17 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
                 if constexpr (ST == ST_PLAIN) {
                     mom_add_all<R, true>(M, vT, vY);
                 } else {
-                    // ring cells need only the two masses (their colour
-                    // fields); the branch is uniform per wave
-                    // (the rest link, then one opposite pair at a time)
+                    // the rest link, then one opposite pair at a time; the
+                    // LDS reads of the next pair's coefficients are issued
+                    // before the current pair is decoded, so their latency
+                    // overlaps that arithmetic.  Ring cells need only the two
+                    // masses (their colour fields); the branch is uniform per
+                    // wave.
                     auto decode_all = [&]<bool FULL>() {
+                        EqCell nA = coef.template operator()<1>(p), nB = coef.template operator()<2>(p);
                         {
                             R T, Y;
-                            decode.template operator()<0>(p, vT[0], vY[0], T, Y);
+                            dec_link<ST, 0>(P, coef.template operator()<0>(p), vT[0], T, Y);
                             mom_add<R, 0, FULL>(M, T, Y);
                             __builtin_amdgcn_sched_barrier(0);
                         }
@@ -679,9 +679,14 @@ __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__re
                             (
                                 [&] {
                                     constexpr int I = 2 * K + 1;
+                                    const EqCell cA = nA, cB = nB;
+                                    if constexpr (I + 2 < lbq::Q) {
+                                        nA = coef.template operator()<I + 2>(p);
+                                        nB = coef.template operator()<I + 3>(p);
+                                    }
                                     R Ta, Ya, Tb, Yb;
-                                    decode.template operator()<I>(p, vT[I], vY[I], Ta, Ya);
-                                    decode.template operator()<I + 1>(p, vT[I + 1], vY[I + 1], Tb, Yb);
+                                    dec_link<ST, I>(P, cA, vT[I], Ta, Ya);
+                                    dec_link<ST, I + 1>(P, cB, vT[I + 1], Tb, Yb);
                                     mom_add_pair<R, I, FULL>(M, Ta, Ya, Tb, Yb);
                                     __builtin_amdgcn_sched_barrier(0);
                                 }(),
