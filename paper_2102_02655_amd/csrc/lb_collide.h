@@ -331,11 +331,12 @@ __device__ __forceinline__ void collide_state(const DevParams &P, const CellStat
     } else {
         store_all_dev<ST>(P, K, rY, rB, vx, vy, vz, fresh_global(dst), fresh_uniform(pstride), cellb);
         const long long NM = P.NM;
-        mo_dst[cell] = rY;
-        mo_dst[NM + cell] = rB;
-        mo_dst[2 * NM + cell] = vx;
-        mo_dst[3 * NM + cell] = vy;
-        mo_dst[4 * NM + cell] = vz;
+        const auto md = as_global(mo_dst);
+        md[cell] = rY;
+        md[NM + cell] = rB;
+        md[2 * NM + cell] = vx;
+        md[3 * NM + cell] = vy;
+        md[4 * NM + cell] = vz;
     }
     out_rY = rY;
     out_rB = rB;

@@ -644,6 +644,15 @@ __device__ __forceinline__ T fresh_uniform(T v)
 typedef __attribute__((address_space(1))) char gchar;
 typedef __attribute__((address_space(1))) const char gcchar;
 
+// The same pointer in the global address space: global instructions count
+// only against the vector-memory counter, where flat ones count against the
+// LDS counter as well (a wait for an LDS read would also wait for them).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 template <typename P>
 __device__ __forceinline__ gchar *fresh_global(P *p)
 {

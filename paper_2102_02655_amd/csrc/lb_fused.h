@@ -385,11 +385,18 @@ __global__ __launch_bounds__((TY + 3) * 64, 2) void k_fused(DevParams P, StepGeo
 template <typename R, int TY, bool FIRST, int ST = ST_PLAIN, int CR = 1>
 __device__ __forceinline__ void fused_pc_body(const DevParams &P, StepGeom *__restrict__ G, const FusedGrid &FG,
                                               const void *__restrict__ src, void *__restrict__ dst,
-                                              const double *__restrict__ momd, const R *__restrict__ mom,
-                                              const R *__restrict__ chi, const R *__restrict__ ghost,
-                                              R *__restrict__ mac_next, const float *__restrict__ mo_src,
+                                              const double *__restrict__ momd_p, const R *__restrict__ mom_p,
+                                              const R *__restrict__ chi_p, const R *__restrict__ ghost_p,
+                                              R *__restrict__ mac_next_p, const float *__restrict__ mo_src_p,
                                               float *__restrict__ mo_dst, int bid, int nblk)
 {
+    // every array through global (not flat) instructions
+    const auto momd = as_global(momd_p);
+    const auto mom = as_global(mom_p);
+    const auto chi = as_global(chi_p);
+    const auto ghost = as_global(ghost_p);
+    const auto mac_next = as_global(mac_next_p);
+    const auto mo_src = as_global(mo_src_p);
     // E: stored element type; reduced storage keeps 16-bit deviations and
     // decodes them with the source cells' moments (an LDS ring of planes, the
     // tile with a two-cell halo: the ring cells' sources included)
