@@ -89,6 +89,16 @@ struct DevParams {
     float eqf[6];
 };
 
+// The same pointer in the global address space: global instructions count
+// only against the vector-memory counter, where flat ones count against the
+// LDS counter as well (a wait for an LDS read would also wait for them).
+// Every array of the kernels lives in global memory.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Head axis of the previous and the current step, wrapped into the box.
 struct HeadPos {
     double hx_p, hy_p, hx_c, hy_c;
@@ -435,9 +445,9 @@ struct PopSrc {
     __device__ __forceinline__ Raw load_raw(int plane, long long cell) const
     {
         Raw r;
-        r.w = s[plane * NP + cell];
+        r.w = as_global(s)[plane * NP + cell];
 #pragma unroll
-        for (int k = 0; k < NMO; ++k) r.m[k] = mo[k * NM + cell];
+        for (int k = 0; k < NMO; ++k) r.m[k] = as_global(mo)[k * NM + cell];
         return r;
     }
     template <int I>
@@ -461,7 +471,7 @@ struct PopSrc<R, ST_PLAIN> {
     };
     __device__ __forceinline__ Raw load_raw(int plane, long long cell) const
     {
-        return Raw{s[plane * NP + cell], s[(lbq::Q + plane) * NP + cell]};
+        return Raw{as_global(s)[plane * NP + cell], as_global(s)[(lbq::Q + plane) * NP + cell]};
     }
     template <int I>
     __device__ __forceinline__ void finish(const DevParams &, const Raw &r, R &T, R &Y) const
@@ -472,8 +482,8 @@ struct PopSrc<R, ST_PLAIN> {
     template <int I>
     __device__ __forceinline__ void get(const DevParams &, long long cell, R &T, R &Y) const
     {
-        T = s[I * NP + cell];
-        Y = s[(lbq::Q + I) * NP + cell];
+        T = as_global(s)[I * NP + cell];
+        Y = as_global(s)[(lbq::Q + I) * NP + cell];
     }
 };
 
@@ -496,14 +506,14 @@ __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, 
         const bool lo = st == ST_OPEN_LO;
         const double rw0 = lo ? P.rho_lo[0] : P.rho_hi[0], rw1 = lo ? P.rho_lo[1] : P.rho_hi[1];
         // u_w = (3 u(x) - u(x + c_i)) / 2 at t-1 when x + c_i was fluid
-        R ux = mac[2 * N + acell], uy = mac[3 * N + acell], uz = mac[4 * N + acell];
+        R ux = as_global(mac)[2 * N + acell], uy = as_global(mac)[3 * N + acell], uz = as_global(mac)[4 * N + acell];
         int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
         int s1 = classify_cc(P, cc[1 + X][1 + Yc], z1, near);
         if (s1 == ST_FLUID) {
             const long long c1 = aidx(P, x1, y1, z1);
-            ux = (R(3) * ux - mac[2 * N + c1]) * R(0.5);
-            uy = (R(3) * uy - mac[3 * N + c1]) * R(0.5);
-            uz = (R(3) * uz - mac[4 * N + c1]) * R(0.5);
+            ux = (R(3) * ux - as_global(mac)[2 * N + c1]) * R(0.5);
+            uy = (R(3) * uy - as_global(mac)[3 * N + c1]) * R(0.5);
+            uz = (R(3) * uz - as_global(mac)[4 * N + c1]) * R(0.5);
         }
         R cu = R(X) * ux + R(Yc) * uy + R(Z) * uz;
         R uu = ux * ux + uy * uy + uz * uz;
@@ -537,17 +547,17 @@ __device__ __forceinline__ void pull_rule(const DevParams &P, const HeadPos &H, 
             if (U0 * X + U1 * Yc + U2 * Z != 0.0) {
                 // rho_w by quadratic extrapolation to the link midpoint from
                 // x, x + c_i, x + 2 c_i (the inward direction), at t-1
-                R r0Y = mac[0 * N + acell], r0B = mac[1 * N + acell];
+                R r0Y = as_global(mac)[0 * N + acell], r0B = as_global(mac)[1 * N + acell];
                 int x1 = X ? wrap(x + X, P.nx) : x, y1 = Yc ? wrap(y + Yc, P.ny) : y, z1 = z + Z;
                 int s1 = classify_cc(P, cc[1 + X][1 + Yc], z1, near);
                 if (s1 == ST_FLUID) {
                     const long long c1 = aidx(P, x1, y1, z1);
-                    R r1Y = mac[0 * N + c1], r1B = mac[1 * N + c1];
+                    R r1Y = as_global(mac)[0 * N + c1], r1B = as_global(mac)[1 * N + c1];
                     int x2 = X ? wrap(x1 + X, P.nx) : x1, y2 = Yc ? wrap(y1 + Yc, P.ny) : y1, z2 = z1 + Z;
                     int s2 = classify(P, H.hx_p, H.hy_p, x2, y2, z2, near);
                     if (s2 == ST_FLUID) {
                         const long long c2 = aidx(P, x2, y2, z2);
-                        R r2Y = mac[0 * N + c2], r2B = mac[1 * N + c2];
+                        R r2Y = as_global(mac)[0 * N + c2], r2B = as_global(mac)[1 * N + c2];
                         rwY = (R(15) * r0Y - R(10) * r1Y + R(3) * r2Y) * R(0.125);
                         rwB = (R(15) * r0B - R(10) * r1B + R(3) * r2B) * R(0.125);
                     } else {
@@ -643,15 +653,6 @@ __device__ __forceinline__ T fresh_uniform(T v)
 // global (not flat) instructions with a scalar base.
 typedef __attribute__((address_space(1))) char gchar;
 typedef __attribute__((address_space(1))) const char gcchar;
-
-// The same pointer in the global address space: global instructions count
-// only against the vector-memory counter, where flat ones count against the
-// LDS counter as well (a wait for an LDS read would also wait for them).
-template <typename T>
-__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p)
-{
-    return (__attribute__((address_space(1))) T *)p;
-}
 
 template <typename P>
 __device__ __forceinline__ gchar *fresh_global(P *p)

@@ -155,10 +155,16 @@ __device__ __forceinline__ bool macro_needed(const DevParams &P, const HeadPos &
 template <typename R, int TY, bool FIRST>
 __device__ __forceinline__ void fused_body(const DevParams &P, StepGeom *__restrict__ G, const FusedGrid &FG,
                                            const R *__restrict__ src, R *__restrict__ dst,
-                                           const double *__restrict__ momd, const R *__restrict__ mom,
-                                           const R *__restrict__ chi, const R *__restrict__ ghost,
-                                           R *__restrict__ mac_next, int bid, int nblk)
+                                           const double *__restrict__ momd_p, const R *__restrict__ mom_p,
+                                           const R *__restrict__ chi_p, const R *__restrict__ ghost_p,
+                                           R *__restrict__ mac_next_p, int bid, int nblk)
 {
+    // every array through global (not flat) instructions
+    const auto momd = as_global(momd_p);
+    const auto mom = as_global(mom_p);
+    const auto chi = as_global(chi_p);
+    const auto ghost = as_global(ghost_p);
+    const auto mac_next = as_global(mac_next_p);
     constexpr int W = 66, HH = TY + 2, PL = W * HH, NI = TY * 64;
     const HeadPos H = G->H;
     const Box3 head = G->bx[0];

@@ -95,17 +95,17 @@ __device__ __forceinline__ void write_chi(const DevParams &P, R *chi, long long 
 {
     double cN, cY, cB;
     chi_of<double>(P, rY, rB, cN, cY, cB);
-    chi[cell] = R(cN);
-    chi[st + cell] = R(cY);
-    chi[2 * st + cell] = R(cB);
+    as_global(chi)[cell] = R(cN);
+    as_global(chi)[st + cell] = R(cY);
+    as_global(chi)[2 * st + cell] = R(cB);
 }
 
 // densities of a fluid cell from its FP64 masses (slot c, component stride st)
 __device__ __forceinline__ void dens(const DevParams &P, const double *__restrict__ momd, long long c, long long st,
                                     double &rY, double &rB)
 {
-    rY = momd[st + c];
-    rB = P.rho_ref + momd[c] - rY;
+    rY = as_global(momd)[st + c];
+    rB = P.rho_ref + as_global(momd)[c] - rY;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -175,16 +175,16 @@ __device__ __forceinline__ void moments_cell(const DevParams &P, const HeadPos &
     pull_all<R, true>(P, H, src, mac, x, y, z, cell, near, first, M, fl);
     if (!sc) {
         if constexpr (RO) {
-            momd[cell] = M.dm[0];
-            momd[P.N + cell] = M.dm[1];
+            as_global(momd)[cell] = M.dm[0];
+            as_global(momd)[P.N + cell] = M.dm[1];
 #pragma unroll
-            for (int q = 2; q < 5; ++q) mom[(q - 2) * P.N + cell] = M.m[q];
+            for (int q = 2; q < 5; ++q) as_global(mom)[(q - 2) * P.N + cell] = M.m[q];
         } else {
             const long long a = aidx(P, x, y, z), NA = P.NA;
-            momd[a] = M.dm[0];
-            momd[NA + a] = M.dm[1];
+            as_global(momd)[a] = M.dm[0];
+            as_global(momd)[NA + a] = M.dm[1];
 #pragma unroll
-            for (int q = 2; q < NMOM; ++q) mom[(q - 2) * NA + a] = M.m[q];
+            for (int q = 2; q < NMOM; ++q) as_global(mom)[(q - 2) * NA + a] = M.m[q];
             write_chi<R>(P, chi, a, NA, M.dm[1], P.rho_ref + M.dm[0] - M.dm[1]);
         }
     } else {
@@ -329,9 +329,9 @@ __device__ __forceinline__ void create_body(const DevParams &P, const StepGeom *
         double m[NMOM] = {rho - P.rho_ref, rY, rho * vx, rho * vy, 0.0,
                           iso + rho * vx * vx, iso + rho * vy * vy, iso, rho * vx * vy, 0.0, 0.0,
                           rY * (cY2 + vx * vx), rY * (cY2 + vy * vy), rY * cY2, rY * vx * vy, 0.0, 0.0};
-        momd[cell] = m[0];
-        momd[st + cell] = m[1];
-        for (int q = 2; q < (ro ? 5 : NMOM); ++q) mom[(q - 2) * st + cell] = R(m[q]);
+        as_global(momd)[cell] = m[0];
+        as_global(momd)[st + cell] = m[1];
+        for (int q = 2; q < (ro ? 5 : NMOM); ++q) as_global(mom)[(q - 2) * st + cell] = R(m[q]);
         if (!ro) write_chi<R>(P, chi, cell, st, rY, rB);
         acc[0] += rY;
         acc[1] += rB;
@@ -457,9 +457,9 @@ __device__ __forceinline__ void ghost_body(const DevParams &P, const StepGeom *_
     }
     double cN, cY, cB;
     chi_of<double>(P, rY, rB, cN, cY, cB);
-    ghost[(face * 3 + 0) * plane + c] = R(cN);
-    ghost[(face * 3 + 1) * plane + c] = R(cY);
-    ghost[(face * 3 + 2) * plane + c] = R(cB);
+    as_global(ghost)[(face * 3 + 0) * plane + c] = R(cN);
+    as_global(ghost)[(face * 3 + 1) * plane + c] = R(cY);
+    as_global(ghost)[(face * 3 + 2) * plane + c] = R(cB);
 }
 
 template <typename R>
