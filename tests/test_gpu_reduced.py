@@ -114,6 +114,51 @@ def test_reduced_storage_print_bed_full_size(print_bed_oracle, storage):
     s.close()
 
 
+# Density ratio 10 (alpha_Y = 0.9333, alpha_B = 1/3, rho_Y^0 = 10) on the
+# small printing box: only at unequal alpha are the rest link's equilibrium
+# coefficients g_k of the reduced forms non-zero.  The stored deviations are
+# large next to the slow flow here (ink and head at 0.01), so the errors are
+# larger than at ratio 1: measured after 400 steps BF16 3.3e-4 / 1.2e-4 /
+# 9.9e-3 and FP16 3.3e-5 / 1.4e-5 / 1.0e-3 (rho_Y / rho_B / u); the bounds
+# are ten times those.  The two forms' errors differ by their mantissas
+# (2^-8 against 2^-11 relative), as the rounding of the deviations predicts;
+# an equilibrium that the encoder and a decoder evaluated differently would
+# add an error that does not depend on the storage precision.
+RATIO10_BOUND = {"bf16dev": (4e-3, 1.5e-3, 1e-1), "f16dev": (4e-4, 1.5e-4, 1e-2)}
+
+
+def test_reduced_storage_density_ratio_10():
+    from oracle import oracle as O
+    from paper_2102_02655_amd import lbprint as LB
+
+    ratio = 10.0
+    cfg = W.printing((40, 32, 24), head_x0=(12.0, 15.5), r_in=4.0, tip_z=10.0, head_v=(0.03, 0.011), u_ink=0.02,
+                     n=0.5, sub_u=(0.005, 0.0, 0.0), storage="f64")
+    cfg.update(alpha=(1.0 - (2.0 / 3.0) / ratio, 1.0 / 3.0), rho0=(ratio, 1.0))
+    cfg["nozzle"].update(lid_rho_y=ratio, v=(0.01, 0.005), u_ink=(0.0, 0.0, -0.01))
+    ry, rb = W.nozzle_fields(cfg)
+    o = O.OracleSim(cfg, ry, rb)
+    o.step(400)
+    ref = o.moments()
+    errs = {}
+    for st in ("bf16dev", "f16dev"):
+        s = LB.Sim(dict(cfg, storage=st), ry, rb)
+        c0 = s.moments()[3]
+        s.step(400)
+        g = s.moments(dtype=np.float64)
+        errs[st] = (rel(g[0], ref[0]), rel(g[1], ref[1]), rel(g[2], ref[2]))
+        print(f"ratio 10 {st} 400 steps: rho_Y {errs[st][0]:.2e} rho_B {errs[st][1]:.2e} u {errs[st][2]:.2e}")
+        for e, b in zip(errs[st], RATIO10_BOUND[st]):
+            assert e <= b, (st, errs[st], RATIO10_BOUND[st])
+        c = g[3]
+        for k in range(2):
+            lhs = c["mass"][k] - c0["mass"][k]
+            rhs = c["mass_wall"][k] + c["mass_open"][k] + c["mass_created"][k] - c["mass_deleted"][k]
+            assert abs(lhs - rhs) <= 1e-4 * c["mass"][1], (st, k, lhs, rhs)
+        s.close()
+    assert all(b > 4 * f for b, f in zip(errs["bf16dev"], errs["f16dev"])), errs
+
+
 # The print-bed crop (128x64x32, same head, speeds and rheology as the full
 # box), every storage form against the FP64 oracle.  The default run takes
 # n = 0.5 over 1000 steps (about half a minute of oracle time);
